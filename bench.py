@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark of the QCT hot path on one MI355X.
+
+One step = one pass of the whole path over the batched H2 + Ca workload
+(96 instances: 16 collision energies 1e3..1e5 K x v in {0,2,4} x j in {0,5},
+1042 trajectories each, b uniform in area to 10 a0; 100,032 trajectories):
+instance set-up with Bohr-Sommerfeld levels, initial conditions, adaptive
+RK5(4) propagation of every trajectory to its stop rule, classification and
+Gaussian binning, per-instance cross sections and rates.  All inputs are
+synthetic and seeded; nothing is cached between steps.
+
+Prints one JSON line (metric, value, roofline of the propagation kernel,
+CPU-oracle baseline on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# FP64 operations per RK5(4) trial step of one trajectory on the all-Morse
+# surface (FMA = 2), counted from the propagation kernel's instruction
+# stream; see the measurement section of the design notes.
+F_STEP_MORSE = 2224.0
+PEAK_FP64_VECTOR = 78.6e12   # MI355X, FLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched", choices=["batched", "small"])
+    ap.add_argument("--cpu-stride", type=int, default=25,
+                    help="CPU baseline runs every k-th trajectory id through the oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-procs", type=int, default=16)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, stride, procs):
+    """The oracle as it stands on the host cores, on a stratified sample of
+    the same workload (every stride-th trajectory id of every instance)."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    per = [np.arange(i.first_id, i.first_id + i.n_traj, stride, dtype=np.int64)
+           for i in wl.instances]
+    n = int(sum(len(p) for p in per))
+    t0 = time.perf_counter()
+    recs, _ = oracle.run_workload(wl, per, processes=procs)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "trajectories/s", "cores": procs, "kind": "oracle",
+            "sample": "every %dth trajectory id of all %d instances (%d trajectories), "
+                      "serial C oracle in a %d-process pool, %.1f s"
+                      % (stride, len(wl.instances), n, procs, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(trajectories shard by id range; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import qcams_workloads as W
+    import paper_2304_02731_amd as Q
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    wl = W.config_batched() if args.workload == "batched" else W.config_small()
+    dev = torch.device("cuda", 0)
+    ctx = Q.Context(wl.system, wl.params, device=0)
+    ctx.set_instances(wl.instances)
+    ids = ctx.all_ids()
+    n = ids.numel()
+    st = ctx.new_state(n)
+    out = ctx.new_outcome(n)
+    smp = torch.zeros((Q.NS, n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    prop_times = []
+
+    def step(timed):
+        ctx.set_instances(wl.instances)          # units, levels (a1, a2)
+        ctx.init_conditions(ids, st, smp)        # a3
+        if timed:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        ctx.propagate(st)                        # a4, a5
+        if timed:
+            e1.record(stream)
+            prop_times.append((e0, e1))
+        ctx.classify(st, out)                    # a6
+        xs, hist = ctx.cross_sections(out, ids)  # a7, a8
+        return xs
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        xs = step(True)
+        print("step done", file=sys.stderr, flush=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    prop_ms = float(np.mean([a.elapsed_time(b) for a, b in prop_times]))
+
+    # work of the last step
+    nstep = st.nstep.cpu().numpy().astype(np.int64)
+    nrej = st.nrej.cpu().numpy().astype(np.int64)
+    trial_steps = int(nstep.sum() + nrej.sum())
+    flops = trial_steps * F_STEP_MORSE
+    achieved = flops / (prop_ms * 1e-3) / 1e12
+    lab = out.label.cpu().numpy()
+    dE = out.d[3].cpu().numpy()
+    fin = lab != Q.FAILED
+    res = {
+        "metric": "QCT trajectories/s (FP64, H2+Ca)",
+        "value": n / (ms_step * 1e-3),
+        "unit": "trajectories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_traj": n, "instances": len(wl.instances),
+                   "surface": "H2+Ca all-Morse", "atol": wl.params.atol,
+                   "rtol": wl.params.rtol, "R0": wl.params.R0, "t_stop": wl.params.t_stop,
+                   "r_stop": wl.params.r_stop},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_FP64_VECTOR,
+                     "traffic": None, "kernel": "k_propagate<0,0,0>",
+                     "kernel_ms": prop_ms, "trial_steps": trial_steps,
+                     "flop_per_trial_step": F_STEP_MORSE},
+        "trial_steps_per_s": trial_steps / (ms_step * 1e-3),
+        "max_abs_dE_rel": float(np.abs(dE[fin]).max()) if fin.any() else None,
+        "labels": np.bincount(lab, minlength=6).tolist(),
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_stride, args.cpu_procs)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * qcams.h -- C ABI of the MI355X (gfx950) quasi-classical trajectory library.
+ *
+ * The calls follow the problem statement of Koots & Perez-Rios, "PyQCAMS"
+ * (arXiv:2304.02731): an atom C collides with a diatomic molecule AB on a
+ * pairwise-additive surface (Morse, generalized Lennard-Jones or Buckingham
+ * pairs, Sec. 3.2); each trajectory starts from a Bohr-Sommerfeld (v, j) state
+ * with random orientation and vibrational phase (Sec. 2.1), is integrated with
+ * an adaptive Dormand-Prince RK5(4) (Sec. 2, Eq. (3)-(4); Sec. 3.2), and ends
+ * with classification into quench / reaction / dissociation and Gaussian
+ * binning of the product's (v', j') (Sec. 2.2); cross sections, Monte Carlo
+ * errors and rates follow (Sec. 2.3 Eq. (12)-(16); Sec. 4 Eq. (18)-(19)).
+ *
+ * Conventions for every call:
+ *  - Units: atomic units (hbar = m_e = a0 = E_h = 1), except collision
+ *    energies, which are given in kelvin (as the paper's input file does).
+ *    Masses are in electron masses.
+ *  - Return value: QCAMS_OK (0) or a negative QCAMS_E* code; qcams_last_error
+ *    gives a message.  No exception or abort crosses the ABI.  Problems of a
+ *    single trajectory are reported in its status / label, never as a call
+ *    error.
+ *  - Memory: pointers documented "device" are device memory owned by the
+ *    caller; they must stay valid until the work queued on `stream` has
+ *    finished.  The library never frees or keeps them.  "host" pointers are
+ *    read (or written) before the call returns.  The library owns only the
+ *    context.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *    marked "async" only enqueue kernels on it; calls marked "sync" block.
+ *  - Determinism: every result is a pure function of (system, params,
+ *    instances, seed, trajectory id); integer results are bit-reproducible
+ *    and floating-point reductions use a fixed order.
+ *  - Structure-of-arrays: per-trajectory arrays are laid out field-major with
+ *    a leading dimension `ld` >= the number of trajectories (element i of
+ *    field f at [f * ld + i]).
+ */
+#ifndef QCAMS_H
+#define QCAMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define QCAMS_OK 0
+#define QCAMS_EINVAL (-1)   /* bad argument */
+#define QCAMS_EUNBOUND (-2) /* a requested (v, j) level is not bound */
+#define QCAMS_ENOROOT (-3)  /* a level / shape root could not be bracketed */
+#define QCAMS_EHIP (-4)     /* a HIP runtime call failed */
+#define QCAMS_ENOMEM (-5)   /* device allocation failed */
+
+/* ---- pair potentials (Sec. 3.2; Eq. (17)) ---- */
+#define QCAMS_MORSE 0 /* V = De (1 - exp(-alpha (r - re)))^2 - De;  p = {De, re, alpha} */
+#define QCAMS_LJ 1    /* V = Cn r^-n - Cm r^-m, integers n > m >= 3;  p = {Cn, Cm} */
+#define QCAMS_BUCK 2  /* V = A exp(-b r) - C6 r^-6;  p = {A, b, C6} */
+
+/* ---- impact-parameter sampling ---- */
+#define QCAMS_B_FIXED 0 /* every trajectory at b */
+#define QCAMS_B_AREA 1  /* b = bmax sqrt(U): uniform over the disc of radius bmax */
+
+/* ---- trajectory status ---- */
+#define QCAMS_RUNNING 0
+#define QCAMS_OK_RSTOP 1        /* a pair distance exceeded r_stop (shifted, see below) */
+#define QCAMS_OK_TMAX 2         /* t reached t_max */
+#define QCAMS_FAIL_MAXSTEPS 3   /* max_steps accepted steps without stopping */
+#define QCAMS_FAIL_NONFINITE 4  /* non-finite state */
+#define QCAMS_FAIL_HMIN 5       /* step size fell below 1e-12 t_max */
+#define QCAMS_COLLAPSE 6        /* a Buckingham pair fell inside its inner maximum */
+
+/* ---- outcome labels: the product-count vector (n_q, n_r1, n_r2, n_d), Sec. 3.3 ---- */
+#define QCAMS_QUENCH 0     /* AB bound:  AB(v') + C  */
+#define QCAMS_R1 1         /* CA bound:  AC + B      */
+#define QCAMS_R2 2         /* BC bound:  BC + A      */
+#define QCAMS_DISS 3       /* no pair bound: A + B + C */
+#define QCAMS_UNRESOLVED 4 /* more than one pair bound (the paper requires exactly one) */
+#define QCAMS_FAILED 5     /* the trajectory did not end with OK_RSTOP / OK_TMAX */
+
+typedef struct {
+    int32_t kind; /* QCAMS_MORSE / QCAMS_LJ / QCAMS_BUCK */
+    int32_t n, m; /* LJ exponents (n > m), ignored otherwise */
+    int32_t pad;
+    double p[6];  /* see the kind's comment; unused entries ignored */
+} qcams_pair;
+
+typedef struct {
+    double mass[3];     /* mA, mB, mC in electron masses; AB is the molecule */
+    qcams_pair pair[3]; /* AB, BC, CA */
+} qcams_system;
+
+typedef struct {
+    double R0;       /* distance of the atom from the molecule before the phase shift (a0), Eq. (6) */
+    double t_stop;   /* t_max = t_stop * R / v_c, v_c = collision speed (Sec. 3.1) */
+    double r_stop;   /* stop when a pair distance exceeds r_stop + (R - R0) (Sec. 3.1) */
+    double atol;     /* absolute tolerance of the RK5(4) error control */
+    double rtol;     /* relative tolerance */
+    double gb_sigma; /* Gaussian-binning width of Eq. (11) */
+    double h_fixed;  /* step of fixed-step mode */
+    int32_t fixed_step;    /* 1: no error control, step h_fixed */
+    int32_t literal_bound; /* 1: Eq. (8) alone; 0: also require the pair inside its barrier */
+    int64_t max_steps;     /* accepted steps per trajectory, 1 .. 2^31-1 */
+} qcams_params;
+
+typedef struct {
+    double Ec_K;       /* collision energy (kelvin) */
+    double b;          /* impact parameter for QCAMS_B_FIXED (a0) */
+    double bmax;       /* maximum impact parameter for QCAMS_B_AREA (a0) */
+    int32_t b_mode;    /* QCAMS_B_FIXED / QCAMS_B_AREA */
+    int32_t v, j;      /* initial rovibrational level of AB */
+    int32_t pad;
+    int64_t n_traj;    /* trajectories of this instance */
+    int64_t first_id;  /* global id of its first trajectory; ids are contiguous */
+    uint64_t seed;     /* random stream key (Philox4x64-10, key = (seed, 0)) */
+} qcams_instance;
+
+/* Per-trajectory double fields of the state, [QCAMS_NF][ld] */
+#define QCAMS_NF 18
+#define QCAMS_F_X 0       /* 0..5:  rho1 (3), rho2 (3) -- Jacobi vectors (Sec. 2) */
+#define QCAMS_F_P 6       /* 6..11: P1 (3), P2 (3) -- conjugate momenta */
+#define QCAMS_F_T 12      /* time */
+#define QCAMS_F_TMAX 13   /* t_max */
+#define QCAMS_F_RSTOP 14  /* effective r_stop */
+#define QCAMS_F_E0 15     /* initial total energy H(0) */
+#define QCAMS_F_ESCALE 16 /* energy scale max(|H(0)|, |E_vj|) for the conservation check */
+#define QCAMS_F_H 17      /* next step size (<= 0: choose the starting step) */
+
+typedef struct {
+    double *d;        /* device [QCAMS_NF][ld] */
+    int32_t *nstep;   /* device [ld] accepted steps */
+    int32_t *nrej;    /* device [ld] rejected steps */
+    uint8_t *status;  /* device [ld] QCAMS_RUNNING / QCAMS_OK_* / QCAMS_FAIL_* */
+    int64_t ld;
+} qcams_state;
+
+/* Per-trajectory sample fields, [QCAMS_NS][ld]: b, cos(theta), phi, eta, chi, weight */
+#define QCAMS_NS 6
+
+/* Per-trajectory outcome.  d = [4][ld]: v', j' (Eq. (9)-(10)), Gaussian weight
+ * W (Eq. (11)), (H(t_f) - H(0)) / escale.  (vt, jt, W) = (0, 0, 0) unless
+ * exactly one pair is bound (the paper's s_f for dissociation, Sec. 3.3). */
+typedef struct {
+    uint8_t *label;   /* device [ld] QCAMS_QUENCH .. QCAMS_FAILED */
+    int16_t *vt;      /* device [ld] nearest integer of v' */
+    int16_t *jt;      /* device [ld] nearest integer of j' */
+    double *d;        /* device [4][ld] */
+    int64_t ld;
+} qcams_outcome;
+
+/* Per-instance results, rows of QCAMS_XS_STRIDE doubles:
+ *   [0] N, [1..6] counts per label, [7..10] P_x = (1/N) sum w 1[x] for
+ *   x = q, r1, r2, d (Eq. (13)), [11..14] its Monte Carlo error (Eq. (16)
+ *   when w = 1), [15..18] sigma_x, [19..22] error of sigma_x, [23..26] rate
+ *   k_x = sigma_x sqrt(2 E_c / mu_123) (Eq. (19)), [27] total weight W of
+ *   Eq. (15), [28] sum w, [29] sum w^2.  sigma uses the reading
+ *   sigma = 2 pi int P b db of Eq. (18): pi bmax^2 P for area sampling; NaN
+ *   for fixed-b instances (combine those with a b grid). */
+#define QCAMS_XS_STRIDE 32
+/* Gaussian-binning histograms, [n_inst][3][QCAMS_VMAX]: channel q, r1, r2 by
+ * v_t, sum of w * W (Eq. (14) numerators). */
+#define QCAMS_VMAX 64
+
+typedef struct qcams_ctx qcams_ctx;
+
+/* Create a context on `device` for one system and parameter set.  Finds the
+ * pair shapes (Buckingham inner maximum, potential minimum, the maximum of
+ * r^3 V') on the device.  sync.  Errors: EINVAL (bad masses, kinds, LJ
+ * exponents, tolerances, a potential without the single-well shape),
+ * EHIP, ENOMEM. */
+int qcams_create(qcams_ctx **ctx, int device, const qcams_system *sys,
+                 const qcams_params *prm);
+
+/* Release the context and its device memory.  NULL is allowed. */
+void qcams_destroy(qcams_ctx *ctx);
+
+/* Message of the last error on this context (or of the last failed create
+ * when ctx is NULL).  Owned by the library. */
+const char *qcams_last_error(const qcams_ctx *ctx);
+
+/* Bohr-Sommerfeld levels of AB (Eq. (10) with v' = v, Eq. (7)): for each of
+ * n (v, j) pairs, out[4 i + 0..3] = E_vj (hartree), r-, r+ (turning points,
+ * a0), tau_vj (vibrational period).  v, j, out: host.  sync.  Errors:
+ * EUNBOUND (some level is not bound; its row is NaN), EINVAL. */
+int qcams_levels(qcams_ctx *ctx, int32_t n, const int32_t *v, const int32_t *j, double *out);
+
+/* Install the instance table (host array of n_inst rows, sorted by
+ * first_id, id ranges disjoint) and compute each instance's level on the
+ * device.  sync.  Errors: EINVAL, EUNBOUND. */
+int qcams_set_instances(qcams_ctx *ctx, const qcams_instance *inst, int32_t n_inst);
+
+/* Initial conditions (Sec. 2.1, Eq. (5)-(6)) of trajectories ids[0..n)
+ * (device int64, any order; each id must lie in an installed instance).
+ * Writes st (all fields; h = 0, t = 0, status RUNNING, counters 0) and
+ * sample [QCAMS_NS][st->ld] (device; may be NULL).  A trajectory whose id
+ * is outside every instance, or whose b >= R, gets status FAIL_NONFINITE.
+ * async. */
+int qcams_init_conditions(qcams_ctx *ctx, const int64_t *ids, int64_t n,
+                          const qcams_state *st, double *sample, void *stream);
+
+/* Integrate trajectories 0..n-1 of st with the adaptive RK5(4) (Eq. (3)-(4))
+ * until each stops (status != RUNNING).  Trajectories already stopped are
+ * left untouched.  async. */
+int qcams_propagate(qcams_ctx *ctx, const qcams_state *st, int64_t n, void *stream);
+
+/* Product analysis (Sec. 2.2, Eq. (8)-(11)) of the final states 0..n-1.
+ * async. */
+int qcams_classify(qcams_ctx *ctx, const qcams_state *st, int64_t n, const qcams_outcome *out,
+                   void *stream);
+
+/* Per-instance opacities, Monte Carlo errors, cross sections, rates
+ * (Eq. (12)-(16), (18)-(19)) and Gaussian-binning histograms (Eq. (14)-(15))
+ * from n classified trajectories.  ids (device int64) must be sorted
+ * ascending; weight (device, [n], may be NULL = all 1) are importance
+ * weights.  xs: device [n_inst][QCAMS_XS_STRIDE]; hist: device
+ * [n_inst][3][QCAMS_VMAX] or NULL.  async. */
+int qcams_cross_sections(qcams_ctx *ctx, const qcams_outcome *out, const int64_t *ids,
+                         const double *weight, int64_t n, double *xs, double *hist,
+                         void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCAMS_H */

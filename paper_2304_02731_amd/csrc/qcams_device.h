@@ -1,0 +1,866 @@
+// qcams_device.h -- device-side physics of the QCT hot path (HIP, gfx950).
+//
+// Koots & Perez-Rios, "PyQCAMS" (arXiv:2304.02731):
+//   Sec. 2     Jacobi-coordinate Hamiltonian, Eq. (2); Hamilton's equations,
+//              Eq. (3)-(4).
+//   Sec. 2.1   initial conditions, Eq. (5)-(7).
+//   Sec. 2.2   bound criterion Eq. (8); j' Eq. (9); v' Eq. (10); Gaussian
+//              binning Eq. (11).
+//   Sec. 3.2   Morse / generalized Lennard-Jones / Buckingham pairs; adaptive
+//              Runge-Kutta 5(4) (Dormand-Prince).
+//   Sec. 4     Morse form, Eq. (17).
+//
+// Everything here is FP64.  Functions are __host__ __device__ so that the same
+// arithmetic can be exercised by host-side unit checks; the library itself
+// only ever runs them inside kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define QD __host__ __device__ inline
+
+namespace qd {
+
+// ---------------------------------------------------------------------------
+// constants
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr int kNQ = 48;          // midpoint nodes of the radial quadrature
+constexpr double kRFar = 1.0e5;  // outermost radius searched for a barrier (a0)
+
+enum Kind { MORSE = 0, LJ = 1, BUCK = 2 };
+enum Status { RUNNING = 0, OK_RSTOP = 1, OK_TMAX = 2, FAIL_MAXSTEPS = 3,
+              FAIL_NONFINITE = 4, FAIL_HMIN = 5, COLLAPSE = 6 };
+enum Label { QUENCH = 0, R1 = 1, R2 = 2, DISS = 3, UNRESOLVED = 4, FAILED = 5 };
+
+// one pair interaction (Sec. 3.2)
+struct Pot {
+    int32_t kind, n, m, pad;
+    double p0, p1, p2;   // MORSE {De, re, alpha} | LJ {Cn, Cm, -} | BUCK {A, b, C6}
+};
+
+// Shape of a pair potential beyond its inner limit, found once at set-up.
+// With g(r) = r^3 V'(r), the effective potential V + J2/(2 mu r^2) has a
+// stationary point where g(r) = J2/mu.  For the three families g is negative
+// inside the potential minimum re and has a single maximum gmax at rstar
+// beyond it, so J2/mu < gmax gives exactly one well (in (re, rstar)) and one
+// centrifugal barrier (beyond rstar); J2/mu >= gmax gives no well.
+struct Shape {
+    double rin;     // Buckingham inner maximum (collapse radius), else 0
+    double re;      // potential minimum
+    double rstar;   // maximum of g beyond re
+    double gmax;    // g(rstar)
+};
+
+struct Sys {
+    Pot pot[3];       // AB, BC, CA
+    Shape shape[3];
+    double mu12, mu123, inv_mu12, inv_mu123;
+    double mu_pair[3];
+    double cA, cB;    // mA/(mA+mB), mB/(mA+mB)
+    double rin2[3];   // squared collapse radii (0 when none)
+};
+
+struct Prm {
+    double R0, t_stop, r_stop, atol, rtol, gb_sigma, h_fixed;
+    int32_t fixed_step, literal_bound;
+    int64_t max_steps;
+};
+
+// instance row as stored on the device (levels filled in at set-up)
+struct Inst {
+    double Ec;          // collision energy, hartree
+    double b, bmax;
+    int32_t b_mode, v, j, pad;
+    int64_t n_traj, first_id;
+    uint64_t seed;
+    double Evj, rminus, rplus, tau;
+};
+
+// ---------------------------------------------------------------------------
+// pair potentials with first and second derivatives
+// ---------------------------------------------------------------------------
+// finite test usable on host and device (x - x is NaN for inf and NaN)
+QD bool is_finite(double x) { return x - x == 0.0; }
+
+QD double ipow(double x, int n)
+{
+    double r = 1.0;
+    while (n > 0) {
+        if (n & 1) r *= x;
+        x *= x;
+        n >>= 1;
+    }
+    return r;
+}
+
+QD void pot_morse(const Pot& P, double r, double& V, double& d1, double& d2)
+{
+    const double De = P.p0, re = P.p1, a = P.p2;
+    const double e = exp(-a * (r - re));
+    const double om = 1.0 - e;
+    V = De * om * om - De;
+    d1 = 2.0 * De * a * e * om;
+    d2 = 2.0 * De * a * a * e * (2.0 * e - 1.0);
+}
+
+QD void pot_lj(const Pot& P, double r, double& V, double& d1, double& d2)
+{
+    const double ir = 1.0 / r;
+    const double tn = P.p0 * ipow(ir, P.n);   // Cn r^-n
+    const double tm = P.p1 * ipow(ir, P.m);   // Cm r^-m
+    V = tn - tm;
+    d1 = (-P.n * tn + P.m * tm) * ir;
+    d2 = ((P.n * (P.n + 1.0)) * tn - (P.m * (P.m + 1.0)) * tm) * ir * ir;
+}
+
+QD void pot_buck(const Pot& P, double r, double& V, double& d1, double& d2)
+{
+    const double A = P.p0, b = P.p1, C6 = P.p2;
+    const double ir = 1.0 / r, ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
+    const double ex = A * exp(-b * r);
+    V = ex - C6 * ir6;
+    d1 = -b * ex + 6.0 * C6 * ir6 * ir;
+    d2 = b * b * ex - 42.0 * C6 * ir6 * ir2;
+}
+
+QD void pot_all(const Pot& P, double r, double& V, double& d1, double& d2)
+{
+    if (P.kind == MORSE) pot_morse(P, r, V, d1, d2);
+    else if (P.kind == LJ) pot_lj(P, r, V, d1, d2);
+    else pot_buck(P, r, V, d1, d2);
+}
+
+QD double pot_V(const Pot& P, double r)
+{
+    double V, a, b;
+    pot_all(P, r, V, a, b);
+    return V;
+}
+
+// V'(r)/r for the force, specialised per kind at compile time (K >= 0) or
+// selected at run time (K < 0; the kind is uniform across the wave).
+template <int K>
+QD double dV_over_r(const Pot& P, double r, double ir)
+{
+    const int kind = K >= 0 ? K : P.kind;
+    if (kind == MORSE) {
+        const double e = exp(-P.p2 * (r - P.p1));
+        return 2.0 * P.p0 * P.p2 * e * (1.0 - e) * ir;
+    } else if (kind == LJ) {
+        const double tn = P.p0 * ipow(ir, P.n), tm = P.p1 * ipow(ir, P.m);
+        return (-P.n * tn + P.m * tm) * ir * ir;
+    } else {
+        const double ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
+        return (-P.p1 * P.p0 * exp(-P.p1 * r) * ir) + 6.0 * P.p2 * ir6 * ir2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hamilton's equations (Eq. (3)-(4)) in separable form.
+// x = (rho1, rho2), p = (P1, P2).  dx/dt = p / mu is linear, so only the
+// force F(x) = -dV/dx is evaluated.  READING of the Jacobi signs (not fixed by
+// the paper): rho1 = r_B - r_A, rho2 = r_C - R_cm(AB); pair vectors
+// r_AB = rho1, r_BC = rho2 - cA rho1, r_CA = -rho2 - cB rho1.
+// Outputs the squared pair distances (for the stop rules) as a by-product.
+// ---------------------------------------------------------------------------
+template <int K0, int K1, int K2>
+QD void force(const Sys& S, const double* x, double* F, double* s2)
+{
+    double rab[3], rbc[3], rca[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rab[a] = x[a];
+        rbc[a] = x[3 + a] - S.cA * x[a];
+        rca[a] = -x[3 + a] - S.cB * x[a];
+    }
+    const double sab = rab[0] * rab[0] + rab[1] * rab[1] + rab[2] * rab[2];
+    const double sbc = rbc[0] * rbc[0] + rbc[1] * rbc[1] + rbc[2] * rbc[2];
+    const double sca = rca[0] * rca[0] + rca[1] * rca[1] + rca[2] * rca[2];
+    const double dab = sqrt(sab), dbc = sqrt(sbc), dca = sqrt(sca);
+    const double gab = dV_over_r<K0>(S.pot[0], dab, 1.0 / dab);
+    const double gbc = dV_over_r<K1>(S.pot[1], dbc, 1.0 / dbc);
+    const double gca = dV_over_r<K2>(S.pot[2], dca, 1.0 / dca);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // -dV/drho1 = -g_AB r_AB + cA g_BC r_BC + cB g_CA r_CA
+        F[a] = -gab * rab[a] + S.cA * gbc * rbc[a] + S.cB * gca * rca[a];
+        // -dV/drho2 = -g_BC r_BC + g_CA r_CA
+        F[3 + a] = -gbc * rbc[a] + gca * rca[a];
+    }
+    s2[0] = sab;
+    s2[1] = sbc;
+    s2[2] = sca;
+}
+
+QD double hamiltonian(const Sys& S, const double* x, const double* p)
+{
+    double T = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        T += 0.5 * p[a] * p[a] * S.inv_mu12;
+        T += 0.5 * p[3 + a] * p[3 + a] * S.inv_mu123;
+    }
+    double r[3];
+    double rbc[3], rca[3];
+    for (int a = 0; a < 3; ++a) {
+        rbc[a] = x[3 + a] - S.cA * x[a];
+        rca[a] = -x[3 + a] - S.cB * x[a];
+    }
+    r[0] = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    r[1] = sqrt(rbc[0] * rbc[0] + rbc[1] * rbc[1] + rbc[2] * rbc[2]);
+    r[2] = sqrt(rca[0] * rca[0] + rca[1] * rca[1] + rca[2] * rca[2]);
+    return T + pot_V(S.pot[0], r[0]) + pot_V(S.pot[1], r[1]) + pot_V(S.pot[2], r[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Dormand-Prince 5(4), rewritten for the separable system.
+//
+// With v = p/mu and stage forces F_l, the stage positions are
+//   X_i = x + h c_i v + (h^2/mu) sum_l (A^2)_il F_l
+// and the step is
+//   x' = x + h v + (h^2/mu) sum_l (bA)_l F_l,   p' = p + h sum_l b_l F_l,
+// with error estimate
+//   e_x = (h^2/mu) sum_l (eA)_l F_l,            e_p = h sum_l e_l F_l,
+// e = b - bhat.  This is algebraically the same method as applying the
+// tableau to the 12-component first-order system, but only the 6 force
+// components of each stage are stored (half the registers).  X_7 = x', so
+// F_7 is reused as F_1 of the next step (first same as last).
+// ---------------------------------------------------------------------------
+namespace dp {
+// Butcher tableau of Dormand & Prince (1980)
+constexpr double c2 = 1.0 / 5, c3 = 3.0 / 10, c4 = 4.0 / 5, c5 = 8.0 / 9;
+constexpr double a21 = 1.0 / 5;
+constexpr double a31 = 3.0 / 40, a32 = 9.0 / 40;
+constexpr double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;
+constexpr double a51 = 19372.0 / 6561, a52 = -25360.0 / 2187, a53 = 64448.0 / 6561,
+                 a54 = -212.0 / 729;
+constexpr double a61 = 9017.0 / 3168, a62 = -355.0 / 33, a63 = 46732.0 / 5247,
+                 a64 = 49.0 / 176, a65 = -5103.0 / 18656;
+constexpr double b1 = 35.0 / 384, b3 = 500.0 / 1113, b4 = 125.0 / 192,
+                 b5 = -2187.0 / 6784, b6 = 11.0 / 84;
+constexpr double bh1 = 5179.0 / 57600, bh3 = 7571.0 / 16695, bh4 = 393.0 / 640,
+                 bh5 = -92097.0 / 339200, bh6 = 187.0 / 2100, bh7 = 1.0 / 40;
+constexpr double e1 = b1 - bh1, e3 = b3 - bh3, e4 = b4 - bh4, e5 = b5 - bh5,
+                 e6 = b6 - bh6, e7 = -bh7;
+// (A^2)_il = sum_j a_ij a_jl  (rows 3..6; row 2 is zero)
+constexpr double q31 = a32 * a21;
+constexpr double q41 = a42 * a21 + a43 * a31, q42 = a43 * a32;
+constexpr double q51 = a52 * a21 + a53 * a31 + a54 * a41, q52 = a53 * a32 + a54 * a42,
+                 q53 = a54 * a43;
+constexpr double q61 = a62 * a21 + a63 * a31 + a64 * a41 + a65 * a51,
+                 q62 = a63 * a32 + a64 * a42 + a65 * a52, q63 = a64 * a43 + a65 * a53,
+                 q64 = a65 * a54;
+// (bA)_l = sum_i b_i a_il
+constexpr double w1 = b3 * a31 + b4 * a41 + b5 * a51 + b6 * a61;
+constexpr double w2 = b3 * a32 + b4 * a42 + b5 * a52 + b6 * a62;
+constexpr double w3 = b4 * a43 + b5 * a53 + b6 * a63;
+constexpr double w4 = b5 * a54 + b6 * a64;
+constexpr double w5 = b6 * a65;
+// (eA)_l = sum_i e_i a_il  (row 7 of A is b)
+constexpr double z1 = e3 * a31 + e4 * a41 + e5 * a51 + e6 * a61 + e7 * b1;
+constexpr double z2 = e3 * a32 + e4 * a42 + e5 * a52 + e6 * a62;
+constexpr double z3 = e4 * a43 + e5 * a53 + e6 * a63 + e7 * b3;
+constexpr double z4 = e5 * a54 + e6 * a64 + e7 * b4;
+constexpr double z5 = e6 * a65 + e7 * b5;
+constexpr double z6 = e7 * b6;
+}  // namespace dp
+
+// One trial step.  In: x, p, F1 = F(x), h.  Out: xn, pn, F7 = F(xn), the
+// squared pair distances at xn, and the RMS error norm of Hairer-Norsett-
+// Wanner (I, Sec. II.4) over the 12 components, scaled by
+// atol + rtol max(|y|, |y'|).
+template <int K0, int K1, int K2>
+QD double dopri5_trial(const Sys& S, const double* x, const double* p, const double* F1,
+                       double h, double atol, double rtol, double* xn, double* pn,
+                       double* F7, double* s2)
+{
+    using namespace dp;
+    double v[6], X[6], F2[6], F3[6], F4[6], F5[6], F6[6], junk[3];
+    const double im[6] = {S.inv_mu12, S.inv_mu12, S.inv_mu12,
+                          S.inv_mu123, S.inv_mu123, S.inv_mu123};
+    const double hh = h * h;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] = p[i] * im[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) X[i] = x[i] + (h * c2) * v[i];
+    force<K0, K1, K2>(S, X, F2, junk);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) X[i] = x[i] + (h * c3) * v[i] + hh * im[i] * (q31 * F1[i]);
+    force<K0, K1, K2>(S, X, F3, junk);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        X[i] = x[i] + (h * c4) * v[i] + hh * im[i] * (q41 * F1[i] + q42 * F2[i]);
+    force<K0, K1, K2>(S, X, F4, junk);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        X[i] = x[i] + (h * c5) * v[i] + hh * im[i] * (q51 * F1[i] + q52 * F2[i] + q53 * F3[i]);
+    force<K0, K1, K2>(S, X, F5, junk);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        X[i] = x[i] + h * v[i] +
+               hh * im[i] * (q61 * F1[i] + q62 * F2[i] + q63 * F3[i] + q64 * F4[i]);
+    force<K0, K1, K2>(S, X, F6, junk);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        xn[i] = x[i] + h * v[i] +
+                hh * im[i] * (w1 * F1[i] + w2 * F2[i] + w3 * F3[i] + w4 * F4[i] + w5 * F5[i]);
+        pn[i] = p[i] + h * (b1 * F1[i] + b3 * F3[i] + b4 * F4[i] + b5 * F5[i] + b6 * F6[i]);
+    }
+    force<K0, K1, K2>(S, xn, F7, s2);
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const double ex = hh * im[i] *
+                          (z1 * F1[i] + z2 * F2[i] + z3 * F3[i] + z4 * F4[i] + z5 * F5[i] +
+                           z6 * F6[i]);
+        const double ep = h * (e1 * F1[i] + e3 * F3[i] + e4 * F4[i] + e5 * F5[i] + e6 * F6[i] +
+                               e7 * F7[i]);
+        const double sx = atol + rtol * fmax(fabs(x[i]), fabs(xn[i]));
+        const double sp = atol + rtol * fmax(fabs(p[i]), fabs(pn[i]));
+        const double qx = ex / sx, qp = ep / sp;
+        acc += qx * qx + qp * qp;
+    }
+    return sqrt(acc * (1.0 / 12.0));
+}
+
+// Starting step (Hairer-Norsett-Wanner I, Sec. II.4), on the 12-component
+// system y = (x, p), f = (p/mu, F).
+template <int K0, int K1, int K2>
+QD double initial_step(const Sys& S, const double* x, const double* p, const double* F0,
+                       double atol, double rtol, double span)
+{
+    const double im[6] = {S.inv_mu12, S.inv_mu12, S.inv_mu12,
+                          S.inv_mu123, S.inv_mu123, S.inv_mu123};
+    double d0 = 0.0, d1 = 0.0;
+    for (int i = 0; i < 6; ++i) {
+        const double sx = atol + rtol * fabs(x[i]), sp = atol + rtol * fabs(p[i]);
+        const double vx = p[i] * im[i];
+        d0 += (x[i] / sx) * (x[i] / sx) + (p[i] / sp) * (p[i] / sp);
+        d1 += (vx / sx) * (vx / sx) + (F0[i] / sp) * (F0[i] / sp);
+    }
+    d0 = sqrt(d0 / 12.0);
+    d1 = sqrt(d1 / 12.0);
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    h0 = fmin(h0, span);
+    double x1[6], p1[6], F1[6], s2[3];
+    for (int i = 0; i < 6; ++i) {
+        x1[i] = x[i] + h0 * p[i] * im[i];
+        p1[i] = p[i] + h0 * F0[i];
+    }
+    force<K0, K1, K2>(S, x1, F1, s2);
+    double d2 = 0.0;
+    for (int i = 0; i < 6; ++i) {
+        const double sx = atol + rtol * fabs(x[i]), sp = atol + rtol * fabs(p[i]);
+        const double dvx = (p1[i] - p[i]) * im[i], dF = F1[i] - F0[i];
+        d2 += (dvx / sx) * (dvx / sx) + (dF / sp) * (dF / sp);
+    }
+    d2 = sqrt(d2 / 12.0) / h0;
+    const double dm = fmax(d1, d2);
+    const double h1 = dm <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 0.2);
+    return fmin(fmin(100.0 * h0, h1), span);
+}
+
+// ---------------------------------------------------------------------------
+// Per-lane trajectory state kept in registers while in flight.
+// ---------------------------------------------------------------------------
+struct Lane {
+    double x[6], p[6], F[6];
+    double t, tmax, rstop2, h;
+    int32_t nstep, nrej, status, last_rej;
+};
+
+// Advance one lane by one trial step with the paper's adaptive RK5(4) and the
+// stop rules (READING of Sec. 3.1: stop after the first accepted step with
+// the largest pair distance beyond r_stop_eff -- squares compared --, or at
+// t_max; fail on step count, non-finite state, step-size underflow, or a pair
+// inside a Buckingham inner maximum).  Step control: accept iff err <= 1,
+// h <- h min(10, max(0.2, 0.9 err^-1/5)), no increase right after a rejection,
+// h_min = 1e-12 t_max.
+template <int K0, int K1, int K2>
+QD void lane_step(const Sys& S, const Prm& P, Lane& L)
+{
+    double xn[6], pn[6], Fn[6], s2[3];
+    const double span = L.tmax - L.t;
+    const double hs = fmin(L.h, span);
+    double err = dopri5_trial<K0, K1, K2>(S, L.x, L.p, L.F, hs, P.atol, P.rtol, xn, pn, Fn, s2);
+    if (P.fixed_step) err = 0.0;
+    if (!(err <= 1.0e300)) err = INFINITY;   // NaN or inf: reject
+    if (err <= 1.0) {
+        L.t = (hs == span) ? L.tmax : L.t + hs;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            L.x[i] = xn[i];
+            L.p[i] = pn[i];
+            L.F[i] = Fn[i];
+        }
+        L.nstep += 1;
+        bool finite = true;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) finite = finite && is_finite(xn[i]) && is_finite(pn[i]);
+        const double m2 = fmax(s2[0], fmax(s2[1], s2[2]));
+        const bool collapsed = s2[0] < S.rin2[0] || s2[1] < S.rin2[1] || s2[2] < S.rin2[2];
+        if (!finite) L.status = FAIL_NONFINITE;
+        else if (collapsed) L.status = COLLAPSE;
+        else if (m2 > L.rstop2) L.status = OK_RSTOP;
+        else if (L.t >= L.tmax) L.status = OK_TMAX;
+        if (!P.fixed_step) {
+            double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(err, -0.2)));
+            if (L.last_rej && fac > 1.0) fac = 1.0;
+            L.h = hs * fac;
+        }
+        L.last_rej = 0;
+    } else {
+        L.nrej += 1;
+        L.h = hs * fmax(0.2, 0.9 * pow(err, -0.2));
+        L.last_rej = 1;
+    }
+    if (L.status == RUNNING && !P.fixed_step && L.h < 1e-12 * L.tmax) L.status = FAIL_HMIN;
+    if (L.status == RUNNING && L.nstep >= P.max_steps) L.status = FAIL_MAXSTEPS;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+QD void mul128(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo)
+{
+    const unsigned __int128 w = (unsigned __int128)a * b;
+    hi = (uint64_t)(w >> 64);
+    lo = (uint64_t)w;
+}
+
+QD void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t h0, l0, h1, l1;
+        mul128(M0, c[0], h0, l0);
+        mul128(M1, c[2], h1, l1);
+        const uint64_t n0 = h1 ^ c[1] ^ k0, n2 = h0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = l1;
+        c[2] = n2;
+        c[3] = l0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+QD double to_unit(uint64_t u) { return (double)(u >> 11) * 0x1.0p-53; }
+
+// Five uniforms of trajectory `id`: words 0-3 of block 0 and word 0 of
+// block 1 of the stream keyed by (seed, 0), counter (id, block, 0, 0).
+QD void uniforms5(uint64_t seed, int64_t id, double* u)
+{
+    uint64_t c[4] = {(uint64_t)id, 0, 0, 0};
+    philox4x64(c, seed, 0);
+    u[0] = to_unit(c[0]);
+    u[1] = to_unit(c[1]);
+    u[2] = to_unit(c[2]);
+    u[3] = to_unit(c[3]);
+    uint64_t d[4] = {(uint64_t)id, 1, 0, 0};
+    philox4x64(d, seed, 0);
+    u[4] = to_unit(d[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Initial conditions (Sec. 2.1).  Fills x, p; returns t_max, r_stop_eff and
+// the sampled (b, cos theta, phi, eta, chi).  Returns false if b >= R.
+// READING: uniform d(Omega) measure (cos theta in [-1,1), phi, eta in [0,2pi),
+// chi in [0,1)); b fixed or bmax sqrt(U); atom along +z with b along +y;
+// t_max = t_stop R / v_c; r_stop_eff = r_stop + (R - R0).
+// ---------------------------------------------------------------------------
+QD bool initial_state(const Sys& S, const Prm& P, const Inst& I, int64_t id, double* x,
+                      double* p, double& tmax, double& rstop, double* smp)
+{
+    double u[5];
+    uniforms5(I.seed, id, u);
+    const double b = I.b_mode == 1 ? I.bmax * sqrt(u[0]) : I.b;
+    const double cth = 2.0 * u[1] - 1.0;
+    const double phi = 2.0 * kPi * u[2];
+    const double eta = 2.0 * kPi * u[3];
+    const double chi = u[4];
+    const double sth = sqrt(1.0 - cth * cth);
+    double sph, cph, set, cet;
+    sincos(phi, &sph, &cph);
+    sincos(eta, &set, &cet);
+    const double rp = I.rplus;
+    const double jj = (double)I.j;
+    const double P1 = sqrt(jj * (jj + 1.0)) / rp;
+    // Eq. (5): molecule at r+, momentum perpendicular to rho1
+    x[0] = rp * sth * cph;
+    x[1] = rp * sth * sph;
+    x[2] = rp * cth;
+    p[0] = P1 * (sph * cet - cth * cph * set);
+    p[1] = P1 * (-cph * cet - cth * sph * set);
+    p[2] = P1 * (sth * set);
+    // Eq. (6): vibrational phase through the initial distance
+    const double P2 = sqrt(2.0 * S.mu123 * I.Ec);
+    const double R = P.R0 + chi * P2 * I.tau * S.inv_mu123;
+    x[3] = 0.0;
+    x[4] = b;
+    x[5] = -sqrt(R * R - b * b);
+    p[3] = 0.0;
+    p[4] = 0.0;
+    p[5] = P2;
+    const double vc = P2 * S.inv_mu123;
+    tmax = P.t_stop * R / vc;
+    rstop = P.r_stop + (R - P.R0);
+    smp[0] = b;
+    smp[1] = cth;
+    smp[2] = phi;
+    smp[3] = eta;
+    smp[4] = chi;
+    return b < R;
+}
+
+// ---------------------------------------------------------------------------
+// Radial structure of one pair: well, barrier, turning points, action, period
+// ---------------------------------------------------------------------------
+// g(r) = r^3 V'(r) and its derivative
+QD void gfun(const Pot& P, double r, double& g, double& dg)
+{
+    double V, d1, d2;
+    pot_all(P, r, V, d1, d2);
+    g = r * r * r * d1;
+    dg = r * r * (3.0 * d1 + r * d2);
+}
+
+// Root of g(r) = q on a bracket [lo, hi] where g - q changes sign, by Newton
+// steps kept inside the bracket (bisection when Newton leaves it).
+QD double solve_g(const Pot& P, double q, double lo, double hi)
+{
+    double glo, dg;
+    gfun(P, lo, glo, dg);
+    const bool inc = glo < q;   // g - q goes from - to + on [lo, hi]
+    double r = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        double g;
+        gfun(P, r, g, dg);
+        const double f = g - q;
+        if (f == 0.0) return r;
+        if ((f < 0.0) == inc) lo = r; else hi = r;
+        double rn = r - f / dg;
+        if (!(rn > lo && rn < hi)) rn = 0.5 * (lo + hi);
+        if (fabs(rn - r) <= 1e-15 * r || hi - lo <= 2e-16 * r) return rn;
+        r = rn;
+    }
+    return r;
+}
+
+struct Radial {
+    bool well;      // the effective potential has a well
+    bool barrier;   // ... and an outer maximum within kRFar
+    double rw, r0;  // well minimum, barrier (inf when none)
+};
+
+// Eq. (8)'s r0, "the local maximum of the effective potential", and the well.
+QD Radial radial(const Pot& P, const Shape& Sh, double mu, double J2)
+{
+    Radial R;
+    const double q = J2 / mu;
+    R.well = false;
+    R.barrier = false;
+    R.rw = Sh.re;
+    R.r0 = INFINITY;
+    if (!(q < Sh.gmax)) return R;
+    R.well = true;
+    if (q <= 0.0) return R;
+    R.rw = solve_g(P, q, Sh.re, Sh.rstar);
+    double gfar, dg;
+    gfun(P, kRFar, gfar, dg);
+    if (gfar >= q) return R;    // no maximum inside kRFar: J2 -> 0 limit
+    // bracket [rstar, hi] with g(hi) < q by doubling
+    double lo = Sh.rstar, hi = 2.0 * Sh.rstar;
+    for (int it = 0; it < 64; ++it) {
+        double g;
+        gfun(P, hi, g, dg);
+        if (g < q || hi >= kRFar) break;
+        lo = hi;
+        hi = fmin(2.0 * hi, kRFar);
+    }
+    R.r0 = solve_g(P, q, lo, hi);
+    R.barrier = true;
+    return R;
+}
+
+QD double veff(const Pot& P, double mu, double J2, double r)
+{
+    return pot_V(P, r) + J2 / (2.0 * mu * r * r);
+}
+
+// Root of V_eff(r) = E on [lo, hi] (V_eff - E changes sign), Newton in a
+// bracket.
+QD double solve_veff(const Pot& P, double mu, double J2, double E, double lo, double hi)
+{
+    const bool inc = veff(P, mu, J2, lo) < E;
+    double r = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        double V, d1, d2;
+        pot_all(P, r, V, d1, d2);
+        const double f = V + J2 / (2.0 * mu * r * r) - E;
+        const double df = d1 - J2 / (mu * r * r * r);
+        if (f == 0.0) return r;
+        if ((f < 0.0) == inc) lo = r; else hi = r;
+        double rn = r - f / df;
+        if (!(rn > lo && rn < hi)) rn = 0.5 * (lo + hi);
+        if (fabs(rn - r) <= 1e-15 * r || hi - lo <= 2e-16 * r) return rn;
+        r = rn;
+    }
+    return r;
+}
+
+// Turning points r- < rw < r+ at energy E (E below the barrier top and above
+// the well bottom).  Returns false when they cannot be bracketed.
+QD bool turning_points(const Pot& P, const Shape& Sh, const Radial& R, double mu, double J2,
+                       double E, double& rm, double& rp)
+{
+    if (!(veff(P, mu, J2, R.rw) < E)) return false;
+    // inner bracket: shrink towards the inner limit until V_eff > E
+    double lo = R.rw;
+    bool ok = false;
+    for (int it = 0; it < 80; ++it) {
+        lo = Sh.rin > 0.0 ? Sh.rin + 0.5 * (lo - Sh.rin) : 0.5 * lo;
+        if (veff(P, mu, J2, lo) > E) { ok = true; break; }
+    }
+    if (!ok) return false;
+    double hi = R.rw;
+    ok = false;
+    const double top = R.barrier ? R.r0 : kRFar;
+    for (int it = 0; it < 80; ++it) {
+        hi = fmin(2.0 * hi, top);
+        if (veff(P, mu, J2, hi) > E) { ok = true; break; }
+        if (hi >= top) break;
+    }
+    if (!ok) return false;
+    rm = solve_veff(P, mu, J2, E, lo, R.rw);
+    rp = solve_veff(P, mu, J2, E, R.rw, hi);
+    return true;
+}
+
+// Action and period between the turning points: with r = c + h cos(theta)
+// the integrands of Eq. (10) and Eq. (7) become smooth, even and periodic in
+// theta, so the midpoint rule converges geometrically.
+//   act = (sqrt(2mu)/pi) int sqrt(E - V_eff) dr ; per = sqrt(2mu) int dr / sqrt(E - V_eff)
+QD void action_period(const Pot& P, double mu, double J2, double E, double rm, double rp,
+                      double& act, double& per)
+{
+    const double c = 0.5 * (rp + rm), h = 0.5 * (rp - rm);
+    double sa = 0.0, sp = 0.0;
+    for (int k = 0; k < kNQ; ++k) {
+        double st, ct;
+        sincos(kPi * (k + 0.5) / kNQ, &st, &ct);
+        const double r = c + h * ct;
+        double kin = E - veff(P, mu, J2, r);
+        kin = fmax(kin, 0.0);
+        const double sq = sqrt(kin);
+        sa += st * sq;
+        sp += kin > 0.0 ? st / sq : 0.0;
+    }
+    const double s2mu = sqrt(2.0 * mu);
+    act = s2mu / kPi * h * (kPi / kNQ) * sa;
+    per = s2mu * h * (kPi / kNQ) * sp;
+}
+
+// Bohr-Sommerfeld level of the AB molecule: E with act(E) = v + 1/2,
+// safeguarded Newton using d act/dE = per/(2 pi).  Returns 0, or -2 when the
+// level is not bound, -3 when a root cannot be bracketed.
+QD int bs_level(const Pot& P, const Shape& Sh, double mu, int v, int j, double* out)
+{
+    const double J2 = (double)j * (j + 1.0);
+    const Radial R = radial(P, Sh, mu, J2);
+    if (!R.well) return -2;
+    const double Elo = veff(P, mu, J2, R.rw);
+    const double Ehi = R.barrier ? veff(P, mu, J2, R.r0) : 0.0;
+    const double target = v + 0.5;
+    double lo = Elo, hi = Ehi - 1e-13 * fabs(Ehi - Elo);
+    double rm, rp, act, per;
+    if (!turning_points(P, Sh, R, mu, J2, hi, rm, rp)) return -2;
+    action_period(P, mu, J2, hi, rm, rp, act, per);
+    if (!(act > target)) return -2;
+    // start from the harmonic estimate near the bottom of the well
+    double E = lo + (hi - lo) * fmin(0.5, target / act);
+    for (int it = 0; it < 200; ++it) {
+        if (!turning_points(P, Sh, R, mu, J2, E, rm, rp)) return -3;
+        action_period(P, mu, J2, E, rm, rp, act, per);
+        const double f = act - target;
+        if (f < 0.0) lo = E; else hi = E;
+        double En = E - f * 2.0 * kPi / per;
+        if (!(En > lo && En < hi)) En = 0.5 * (lo + hi);
+        const bool done = fabs(En - E) <= 4e-16 * fabs(E) || hi - lo <= 4e-16 * fabs(E);
+        E = En;
+        if (done) break;
+    }
+    if (!turning_points(P, Sh, R, mu, J2, E, rm, rp)) return -3;
+    action_period(P, mu, J2, E, rm, rp, act, per);
+    out[0] = E;
+    out[1] = rm;
+    out[2] = rp;
+    out[3] = per;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Product analysis of one final state (Sec. 2.2)
+// ---------------------------------------------------------------------------
+struct Outcome {
+    int label, vt, jt;
+    double vprime, jprime, w;
+};
+
+QD Outcome classify_state(const Sys& S, const Prm& P, const double* x, const double* p)
+{
+    Outcome o;
+    o.label = DISS;
+    o.vt = 0;
+    o.jt = 0;
+    o.vprime = 0.0;
+    o.jprime = 0.0;
+    o.w = 0.0;
+    double r[3][3], u[3][3];
+    for (int a = 0; a < 3; ++a) {
+        const double v1 = p[a] * S.inv_mu12, v2 = p[3 + a] * S.inv_mu123;
+        r[0][a] = x[a];
+        r[1][a] = x[3 + a] - S.cA * x[a];
+        r[2][a] = -x[3 + a] - S.cB * x[a];
+        u[0][a] = v1;
+        u[1][a] = v2 - S.cA * v1;
+        u[2][a] = -v2 - S.cB * v1;
+    }
+    double E[3], J2[3], d[3];
+    Radial R[3];
+    int nb = 0, which = -1;
+    for (int k = 0; k < 3; ++k) {
+        const double mu = S.mu_pair[k];
+        d[k] = sqrt(r[k][0] * r[k][0] + r[k][1] * r[k][1] + r[k][2] * r[k][2]);
+        const double v2 = u[k][0] * u[k][0] + u[k][1] * u[k][1] + u[k][2] * u[k][2];
+        E[k] = 0.5 * mu * v2 + pot_V(S.pot[k], d[k]);
+        const double Lx = r[k][1] * u[k][2] - r[k][2] * u[k][1];
+        const double Ly = r[k][2] * u[k][0] - r[k][0] * u[k][2];
+        const double Lz = r[k][0] * u[k][1] - r[k][1] * u[k][0];
+        J2[k] = mu * mu * (Lx * Lx + Ly * Ly + Lz * Lz);
+        R[k] = radial(S.pot[k], S.shape[k], mu, J2[k]);
+        bool bound = false;
+        if (R[k].well) {
+            // Eq. (8): below the barrier top (0 when there is no maximum);
+            // READING: unless literal, the pair must also be inside r0
+            const double thr = (R[k].barrier && J2[k] > 0.0) ? veff(S.pot[k], mu, J2[k], R[k].r0)
+                                                             : 0.0;
+            bound = E[k] < thr && (P.literal_bound || d[k] < R[k].r0);
+        }
+        if (bound) {
+            ++nb;
+            which = k;
+        }
+    }
+    if (nb == 0) return o;
+    if (nb > 1) {
+        o.label = UNRESOLVED;
+        return o;
+    }
+    const int k = which;
+    o.label = k == 0 ? QUENCH : (k == 2 ? R1 : R2);
+    const double mu = S.mu_pair[k];
+    // Eq. (9)
+    o.jprime = -0.5 + 0.5 * sqrt(1.0 + 4.0 * J2[k]);
+    o.jt = (int)floor(o.jprime + 0.5);
+    // Eq. (10) with E'_int = the pair energy
+    double rm, rp, act, per;
+    if (!turning_points(S.pot[k], S.shape[k], R[k], mu, J2[k], E[k], rm, rp)) {
+        o.label = UNRESOLVED;
+        o.jt = 0;
+        o.jprime = 0.0;
+        return o;
+    }
+    action_period(S.pot[k], mu, J2[k], E[k], rm, rp, act, per);
+    o.vprime = act - 0.5;
+    // Eq. (11): Gaussian weight about the nearest integer
+    const double n = floor(o.vprime + 0.5);
+    o.vt = (int)n;
+    const double dv = o.vprime - n, sg = P.gb_sigma;
+    o.w = exp(-dv * dv / (2.0 * sg * sg)) / (sg * sqrt(2.0 * kPi));
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// Set-up of the pair shapes (inner limit, minimum, maximum of r^3 V')
+// ---------------------------------------------------------------------------
+QD double dV_only(const Pot& P, double r)
+{
+    double V, d1, d2;
+    pot_all(P, r, V, d1, d2);
+    return d1;
+}
+
+// root of V' on [lo, hi] by bisection (set-up only)
+QD double bisect_dV(const Pot& P, double lo, double hi)
+{
+    const bool inc = dV_only(P, lo) < 0.0;
+    for (int it = 0; it < 400; ++it) {
+        const double m = 0.5 * (lo + hi);
+        if (m <= lo || m >= hi) break;
+        if ((dV_only(P, m) < 0.0) == inc) lo = m; else hi = m;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Returns 0 on success, -1 if the potential does not have the expected shape.
+QD int pair_shape(const Pot& P, Shape& Sh)
+{
+    Sh.rin = 0.0;
+    double r = 1e-3;
+    if (P.kind == BUCK) {
+        // inner maximum: V' goes from + to - (geometric scan, then bisection)
+        if (!(dV_only(P, r) > 0.0)) return -1;
+        bool found = false;
+        for (int it = 0; it < 4000 && r < kRFar; ++it) {
+            const double r2 = r * 1.01;
+            if (dV_only(P, r2) < 0.0) { Sh.rin = bisect_dV(P, r, r2); r = r2; found = true; break; }
+            r = r2;
+        }
+        if (!found) return -1;
+    } else {
+        r = 0.05;
+    }
+    // minimum: V' goes from - to +
+    if (!(dV_only(P, r) < 0.0)) return -1;
+    bool found = false;
+    for (int it = 0; it < 4000 && r < kRFar; ++it) {
+        const double r2 = r * 1.01;
+        if (dV_only(P, r2) > 0.0) { Sh.re = bisect_dV(P, r, r2); found = true; break; }
+        r = r2;
+    }
+    if (!found) return -1;
+    // maximum of g = r^3 V' beyond re: dg goes from + to -
+    r = Sh.re * 1.0000001;
+    double g, dg;
+    gfun(P, r, g, dg);
+    if (!(dg > 0.0)) return -1;
+    found = false;
+    double lo = r, hi = r;
+    for (int it = 0; it < 4000 && r < kRFar; ++it) {
+        const double r2 = r * 1.01;
+        gfun(P, r2, g, dg);
+        if (dg < 0.0) { lo = r; hi = r2; found = true; break; }
+        r = r2;
+    }
+    if (!found) return -1;
+    for (int it = 0; it < 400; ++it) {
+        const double m = 0.5 * (lo + hi);
+        if (m <= lo || m >= hi) break;
+        gfun(P, m, g, dg);
+        if (dg > 0.0) lo = m; else hi = m;
+    }
+    Sh.rstar = 0.5 * (lo + hi);
+    gfun(P, Sh.rstar, Sh.gmax, dg);
+    // single hump: dg stays negative out to kRFar (coarse check)
+    for (r = hi * 1.05; r < kRFar; r *= 1.05) {
+        gfun(P, r, g, dg);
+        if (dg > 0.0 && g > 1e-300) return -1;
+    }
+    return 0;
+}
+
+}  // namespace qd

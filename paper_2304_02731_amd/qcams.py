@@ -1,0 +1,310 @@
+"""Python binding of the QCT library (include/qcams.h): argument marshalling
+only.  Every step of the path runs in the library's HIP kernels; torch
+provides device memory and streams.
+
+The library must be built (``python -m paper_2304_02731_amd.build``); there is
+no fallback: every call raises if ``libqcams.so`` is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import re
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqcams.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "qcams.h")
+
+# ---- constants mirrored from include/qcams.h ----
+OK, EINVAL, EUNBOUND, ENOROOT, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
+MORSE, LJ, BUCK = 0, 1, 2
+B_FIXED, B_AREA = 0, 1
+RUNNING, OK_RSTOP, OK_TMAX, FAIL_MAXSTEPS, FAIL_NONFINITE, FAIL_HMIN, COLLAPSE = range(7)
+QUENCH, R1, R2, DISS, UNRESOLVED, FAILED = range(6)
+NF, NS, XS_STRIDE, VMAX = 18, 6, 32, 64
+F_X, F_P, F_T, F_TMAX, F_RSTOP, F_E0, F_ESCALE, F_H = 0, 6, 12, 13, 14, 15, 16, 17
+# columns of a cross-section row
+XS_N, XS_COUNTS, XS_P, XS_DP, XS_SIGMA, XS_DSIGMA, XS_RATE, XS_WTOT, XS_SUMW, XS_SUMW2 = \
+    0, 1, 7, 11, 15, 19, 23, 27, 28, 29
+
+# unit conversions of the binding (CODATA 2018)
+AMU_IN_ME = 1822.888486209
+KIND = {"morse": MORSE, "lj": LJ, "buck": BUCK}
+
+
+class QcamsError(RuntimeError):
+    pass
+
+
+class Pair(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("m", C.c_int32), ("pad", C.c_int32),
+                ("p", C.c_double * 6)]
+
+
+class System(C.Structure):
+    _fields_ = [("mass", C.c_double * 3), ("pair", Pair * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [("R0", C.c_double), ("t_stop", C.c_double), ("r_stop", C.c_double),
+                ("atol", C.c_double), ("rtol", C.c_double), ("gb_sigma", C.c_double),
+                ("h_fixed", C.c_double), ("fixed_step", C.c_int32),
+                ("literal_bound", C.c_int32), ("max_steps", C.c_int64)]
+
+
+class Instance(C.Structure):
+    _fields_ = [("Ec_K", C.c_double), ("b", C.c_double), ("bmax", C.c_double),
+                ("b_mode", C.c_int32), ("v", C.c_int32), ("j", C.c_int32), ("pad", C.c_int32),
+                ("n_traj", C.c_int64), ("first_id", C.c_int64), ("seed", C.c_uint64)]
+
+
+class StateC(C.Structure):
+    _fields_ = [("d", C.c_void_p), ("nstep", C.c_void_p), ("nrej", C.c_void_p),
+                ("status", C.c_void_p), ("ld", C.c_int64)]
+
+
+class OutcomeC(C.Structure):
+    _fields_ = [("label", C.c_void_p), ("vt", C.c_void_p), ("jt", C.c_void_p),
+                ("d", C.c_void_p), ("ld", C.c_int64)]
+
+
+_lib = None
+
+
+def exported_names() -> list:
+    """Function names declared in include/qcams.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qcams_[a-z_0-9]+)\s*\(", txt)))
+
+
+def lib():
+    """Load libqcams.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise QcamsError("libqcams.so is not built: run python -m paper_2304_02731_amd.build")
+    import torch  # noqa: F401  (loads the HIP runtime torch uses)
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.qcams_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(System), C.POINTER(Params)]
+    L.qcams_destroy.argtypes = [vp]
+    L.qcams_destroy.restype = None
+    L.qcams_last_error.argtypes = [vp]
+    L.qcams_last_error.restype = C.c_char_p
+    L.qcams_levels.argtypes = [vp, i32, vp, vp, vp]
+    L.qcams_set_instances.argtypes = [vp, C.POINTER(Instance), i32]
+    L.qcams_init_conditions.argtypes = [vp, vp, i64, C.POINTER(StateC), vp, vp]
+    L.qcams_propagate.argtypes = [vp, C.POINTER(StateC), i64, vp]
+    L.qcams_classify.argtypes = [vp, C.POINTER(StateC), i64, C.POINTER(OutcomeC), vp]
+    L.qcams_cross_sections.argtypes = [vp, C.POINTER(OutcomeC), vp, vp, i64, vp, vp, vp]
+    for name in exported_names():
+        getattr(L, name)  # raises if a declared symbol is missing
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------------------
+# conversions of workload descriptions (duck-typed: .masses_amu, .pairs with
+# .kind / .params; params objects with the qcams_params field names)
+# ---------------------------------------------------------------------------
+def make_pair(p) -> Pair:
+    q = Pair()
+    kind = p.kind if isinstance(p.kind, int) else KIND[p.kind]
+    q.kind = kind
+    P = p.params
+    if kind == MORSE:
+        vals = [P["De"], P["re"], P["alpha"]]
+    elif kind == LJ:
+        n, m = int(P["n"]), int(P["m"])
+        q.n, q.m = n, m
+        if "Cn" in P:
+            vals = [P["Cn"], P["Cm"]]
+        else:
+            # depth eps at rm: Cn = eps m rm^n/(n-m), Cm = eps n rm^m/(n-m)
+            eps, rm = float(P["eps"]), float(P["rm"])
+            vals = [eps * m * rm ** n / (n - m), eps * n * rm ** m / (n - m)]
+    else:
+        vals = [P["A"], P["b"], P["C6"]]
+    for i, v in enumerate(vals):
+        q.p[i] = float(v)
+    return q
+
+
+def make_system(system, masses_me: Optional[Sequence[float]] = None) -> System:
+    s = System()
+    m = masses_me if masses_me is not None else [x * AMU_IN_ME for x in system.masses_amu]
+    for i in range(3):
+        s.mass[i] = float(m[i])
+        s.pair[i] = make_pair(system.pairs[i])
+    return s
+
+
+def make_params(p) -> Params:
+    q = Params()
+    for f, _ in Params._fields_:
+        setattr(q, f, getattr(p, f))
+    return q
+
+
+def make_instances(instances) -> C.Array:
+    arr = (Instance * len(instances))()
+    for k, i in enumerate(instances):
+        a = arr[k]
+        a.Ec_K, a.b, a.bmax = i.Ec_K, i.b, i.bmax
+        a.b_mode, a.v, a.j = i.b_mode, i.v, i.j
+        a.n_traj, a.first_id, a.seed = i.n_traj, i.first_id, i.seed
+    return arr
+
+
+# ---------------------------------------------------------------------------
+# device buffers (torch tensors)
+# ---------------------------------------------------------------------------
+@dataclass
+class State:
+    d: "torch.Tensor"        # float64 [NF, ld]
+    nstep: "torch.Tensor"    # int32 [ld]
+    nrej: "torch.Tensor"     # int32 [ld]
+    status: "torch.Tensor"   # uint8 [ld]
+
+    @property
+    def ld(self) -> int:
+        return self.d.shape[1]
+
+    def c(self) -> StateC:
+        return StateC(self.d.data_ptr(), self.nstep.data_ptr(), self.nrej.data_ptr(),
+                      self.status.data_ptr(), self.ld)
+
+
+@dataclass
+class Outcome:
+    label: "torch.Tensor"    # uint8 [ld]
+    vt: "torch.Tensor"       # int16 [ld]
+    jt: "torch.Tensor"       # int16 [ld]
+    d: "torch.Tensor"        # float64 [4, ld]: v', j', W, dE/E
+
+    @property
+    def ld(self) -> int:
+        return self.d.shape[1]
+
+    def c(self) -> OutcomeC:
+        return OutcomeC(self.label.data_ptr(), self.vt.data_ptr(), self.jt.data_ptr(),
+                        self.d.data_ptr(), self.ld)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One system + parameter set on one GPU (qcams_ctx)."""
+
+    def __init__(self, system, params, device: int = 0, masses_me=None):
+        import torch
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        L = lib()
+        self._sys = make_system(system, masses_me)
+        self._prm = make_params(params)
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            rc = L.qcams_create(C.byref(h), device, C.byref(self._sys), C.byref(self._prm))
+        if rc != OK:
+            raise QcamsError("qcams_create failed (%d): %s" % (rc, L.qcams_last_error(None).decode()))
+        self._h = h
+        self.instances = []
+        masses = [self._sys.mass[i] for i in range(3)]
+        self.mu123 = 1.0 / (1.0 / masses[2] + 1.0 / (masses[0] + masses[1]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qcams_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise QcamsError("%s failed (%d): %s" % (what, rc, lib().qcams_last_error(self._h).decode()))
+
+    # ---- synchronous set-up ----
+    def levels(self, v: Sequence[int], j: Sequence[int]) -> np.ndarray:
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        out = np.zeros((len(v), 4))
+        self._check(lib().qcams_levels(self._h, len(v), v.ctypes.data, j.ctypes.data,
+                                       out.ctypes.data), "qcams_levels")
+        return out
+
+    def set_instances(self, instances):
+        arr = make_instances(instances)
+        self._check(lib().qcams_set_instances(self._h, arr, len(instances)), "qcams_set_instances")
+        self.instances = list(instances)
+
+    # ---- buffers ----
+    def new_state(self, n: int) -> State:
+        import torch
+        dev = self.torch_device
+        return State(torch.zeros((NF, n), dtype=torch.float64, device=dev),
+                     torch.zeros(n, dtype=torch.int32, device=dev),
+                     torch.zeros(n, dtype=torch.int32, device=dev),
+                     torch.zeros(n, dtype=torch.uint8, device=dev))
+
+    def new_outcome(self, n: int) -> Outcome:
+        import torch
+        dev = self.torch_device
+        return Outcome(torch.zeros(n, dtype=torch.uint8, device=dev),
+                       torch.zeros(n, dtype=torch.int16, device=dev),
+                       torch.zeros(n, dtype=torch.int16, device=dev),
+                       torch.zeros((4, n), dtype=torch.float64, device=dev))
+
+    # ---- asynchronous path ----
+    def init_conditions(self, ids, state: State, sample=None, stream=None):
+        n = ids.numel()
+        sp = sample.data_ptr() if sample is not None else None
+        self._check(lib().qcams_init_conditions(self._h, ids.data_ptr(), n, C.byref(state.c()),
+                                                sp, _stream(stream)), "qcams_init_conditions")
+
+    def propagate(self, state: State, n: Optional[int] = None, stream=None):
+        n = state.ld if n is None else n
+        self._check(lib().qcams_propagate(self._h, C.byref(state.c()), n, _stream(stream)),
+                    "qcams_propagate")
+
+    def classify(self, state: State, outcome: Outcome, n: Optional[int] = None, stream=None):
+        n = state.ld if n is None else n
+        self._check(lib().qcams_classify(self._h, C.byref(state.c()), n, C.byref(outcome.c()),
+                                         _stream(stream)), "qcams_classify")
+
+    def cross_sections(self, outcome: Outcome, ids, weight=None, n: Optional[int] = None,
+                       with_hist: bool = True, stream=None):
+        import torch
+        n = ids.numel() if n is None else n
+        xs = torch.zeros((len(self.instances), XS_STRIDE), dtype=torch.float64,
+                         device=self.torch_device)
+        hist = torch.zeros((len(self.instances), 3, VMAX), dtype=torch.float64,
+                           device=self.torch_device) if with_hist else None
+        self._check(lib().qcams_cross_sections(
+            self._h, C.byref(outcome.c()), ids.data_ptr(),
+            weight.data_ptr() if weight is not None else None, n, xs.data_ptr(),
+            hist.data_ptr() if hist is not None else None, _stream(stream)),
+            "qcams_cross_sections")
+        return xs, hist
+
+    def all_ids(self):
+        import torch
+        ids = [torch.arange(i.first_id, i.first_id + i.n_traj, dtype=torch.int64)
+               for i in self.instances]
+        return torch.cat(ids).to(self.torch_device)

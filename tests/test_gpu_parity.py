@@ -1,0 +1,388 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Bars: levels and initial states to rounding; samples
+bit-exact; short-horizon phase-space states to 1e-9 relative; labels and
+(v', j') bins bit-exact on the same final state; cross sections on the same
+labels to rounding; cross sections of independent full runs within 3
+combined standard errors."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import qcams_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def Q(torch):
+    import paper_2304_02731_amd as Q
+    Q.lib()
+    return Q
+
+
+def _ctx(Q, wl, **prm):
+    p = dataclasses.replace(wl.params, **prm) if prm else wl.params
+    ctx = Q.Context(wl.system, p, device=0)
+    ctx.set_instances(wl.instances)
+    return ctx
+
+
+def _inst_of(wl, ids):
+    firsts = np.array([i.first_id for i in wl.instances])
+    return np.searchsorted(firsts, ids, side="right") - 1
+
+
+# ----------------------------------------------------------------------------
+def test_levels_match_oracle(Q, orc):
+    for wl in (W.config_batched(), W.config_mixed()):
+        ctx = _ctx(Q, wl)
+        sys = orc.make_system(wl.system)
+        vs, js = zip(*[(v, j) for v in range(0, 6) for j in range(0, 11, 2)])
+        g = ctx.levels(vs, js)
+        for k, (v, j) in enumerate(zip(vs, js)):
+            o = orc.level(sys, v, j)
+            assert g[k, 0] == pytest.approx(o[0], rel=1e-12), (v, j)
+            assert g[k, 1] == pytest.approx(o[1], rel=1e-11), (v, j)
+            assert g[k, 2] == pytest.approx(o[2], rel=1e-11), (v, j)
+            assert g[k, 3] == pytest.approx(o[3], rel=1e-8), (v, j)
+        ctx.close()
+
+
+def test_unbound_level_is_an_error(Q):
+    wl = W.config_small()
+    ctx = _ctx(Q, wl)
+    with pytest.raises(Q.QcamsError, match=r"\(-2\)"):
+        ctx.levels([17], [0])
+    bad = [dataclasses.replace(wl.instances[0], v=40)]
+    with pytest.raises(Q.QcamsError):
+        ctx.set_instances(bad)
+
+
+def test_invalid_arguments(Q):
+    wl = W.config_small()
+    with pytest.raises(Q.QcamsError, match=r"\(-1\)"):
+        Q.Context(wl.system, wl.params, masses_me=[-1.0, 1.0, 1.0])
+    with pytest.raises(Q.QcamsError, match=r"\(-1\)"):
+        Q.Context(wl.system, dataclasses.replace(wl.params, atol=0.0))
+    ctx = _ctx(Q, wl)
+    with pytest.raises(Q.QcamsError, match=r"\(-1\)"):
+        ctx.set_instances([dataclasses.replace(wl.instances[0], bmax=40.0)])
+
+
+# ----------------------------------------------------------------------------
+def _gpu_init(Q, torch, ctx, ids):
+    n = len(ids)
+    tid = torch.as_tensor(np.asarray(ids, dtype=np.int64), device="cuda:0")
+    st = ctx.new_state(n)
+    smp = torch.zeros((Q.NS, n), dtype=torch.float64, device="cuda:0")
+    ctx.init_conditions(tid, st, smp)
+    return tid, st, smp
+
+
+def test_init_matches_oracle(Q, torch, orc):
+    wl = W.config_batched()
+    ctx = _ctx(Q, wl)
+    rng = np.random.default_rng(5)
+    ids = np.sort(rng.choice(wl.n_traj, 777, replace=False))   # several tiles + ragged tail
+    tid, st, smp = _gpu_init(Q, torch, ctx, ids)
+    torch.cuda.synchronize()
+    d, s = st.d.cpu().numpy(), smp.cpu().numpy()
+    assert np.all(st.status.cpu().numpy() == Q.RUNNING)
+    sys, prm = orc.make_system(wl.system), orc.make_params(wl.params)
+    which = _inst_of(wl, ids)
+    levs = {}
+    for c, (i, k) in enumerate(zip(ids, which)):
+        I = wl.instances[k]
+        if k not in levs:
+            levs[k] = orc.level(sys, I.v, I.j)
+        y, aux, sm = orc.init(sys, prm, orc.make_instance(I), levs[k], int(i))
+        assert np.array_equal(s[:5, c], sm[:5]), i            # same draws, bit-exact
+        assert s[5, c] == 1.0
+        rel = np.abs(d[:12, c] - y) / np.maximum(np.abs(y), 1.0)
+        assert rel.max() < 1e-13, (i, rel.max())
+        assert d[Q.F_TMAX, c] == pytest.approx(aux[1], rel=1e-13)
+        assert d[Q.F_RSTOP, c] == pytest.approx(aux[2], rel=1e-14)
+        assert d[Q.F_E0, c] == pytest.approx(aux[3], rel=1e-11, abs=1e-14)
+        assert d[Q.F_ESCALE, c] == pytest.approx(aux[4], rel=1e-11)
+
+
+def test_init_rejects_ids_outside_instances(Q, torch):
+    wl = W.config_small(n_traj=10)
+    ctx = _ctx(Q, wl)
+    tid, st, smp = _gpu_init(Q, torch, ctx, [3, 10, 999, 9])
+    torch.cuda.synchronize()
+    assert st.status.cpu().tolist() == [Q.RUNNING, Q.FAIL_NONFINITE, Q.FAIL_NONFINITE, Q.RUNNING]
+
+
+# ----------------------------------------------------------------------------
+def _short_horizon(Q, torch, orc, wl, ids, periods, **prm):
+    ctx = _ctx(Q, wl, **prm)
+    tid, st, smp = _gpu_init(Q, torch, ctx, ids)
+    sys = orc.make_system(wl.system)
+    p = dataclasses.replace(wl.params, **prm) if prm else wl.params
+    oprm = orc.make_params(p)
+    which = _inst_of(wl, ids)
+    levs = {k: orc.level(sys, wl.instances[k].v, wl.instances[k].j) for k in set(which)}
+    T = np.array([periods * levs[k][3] for k in which])
+    st.d[Q.F_TMAX] = torch.as_tensor(T, device="cuda:0")
+    st.d[Q.F_RSTOP].fill_(1e9)
+    ctx.propagate(st)
+    torch.cuda.synchronize()
+    d = st.d.cpu().numpy()
+    status = st.status.cpu().numpy()
+    nstep = st.nstep.cpu().numpy()
+    worst = 0.0
+    for c, (i, k) in enumerate(zip(ids, which)):
+        I = wl.instances[k]
+        y0, aux, _ = orc.init(sys, oprm, orc.make_instance(I), levs[k], int(i))
+        so, y, a, ns, nr = orc.propagate(sys, oprm, y0, np.r_[0.0, T[c], 1e9, aux[3], aux[4], 0])
+        assert status[c] == so == Q.OK_TMAX
+        assert d[Q.F_T, c] == a[0] == T[c]
+        rel = np.abs(d[:12, c] - y) / np.maximum(np.abs(y), 1.0)
+        worst = max(worst, rel.max())
+        assert rel.max() < 1e-9, (i, rel.max(), nstep[c], ns)
+    return worst
+
+
+def test_short_horizon_states_match(Q, torch, orc):
+    """Five vibrational periods from the initial state, adaptive steps."""
+    wl = W.config_batched()
+    rng = np.random.default_rng(7)
+    ids = np.sort(rng.choice(wl.n_traj, 300, replace=False))
+    worst = _short_horizon(Q, torch, orc, wl, ids, 5.0)
+    print("short-horizon worst relative difference %.2e" % worst)
+
+
+def test_short_horizon_mixed_potentials(Q, torch, orc):
+    """LJ / Morse / Buckingham surface (the specialised kernel for that triple)."""
+    wl = W.config_mixed(per_inst=3)
+    rng = np.random.default_rng(8)
+    ids = np.sort(rng.choice(wl.n_traj, 200, replace=False))
+    _short_horizon(Q, torch, orc, wl, ids, 3.0)
+
+
+def test_short_horizon_generic_kernel(Q, torch, orc):
+    """A kind triple without a specialised kernel (run-time pair dispatch)."""
+    s = W.h2ca_system()
+    bc = W.Pair("buck", {"A": 50.0, "b": 1.5, "C6": 40.0})
+    wl = W.config_batched(per_inst=2)
+    wl.system = W.System(s.masses_amu, (s.pairs[0], bc, s.pairs[2]), "h2 generic")
+    _short_horizon(Q, torch, orc, wl, np.arange(0, 192, 3), 3.0)
+
+
+def test_fixed_step_mode_matches(Q, torch, orc):
+    wl = W.config_batched(per_inst=4)
+    _short_horizon(Q, torch, orc, wl, np.arange(0, 384, 5), 2.0, fixed_step=1, h_fixed=0.5)
+
+
+# ----------------------------------------------------------------------------
+def _oracle_final_states(orc, wl, ids, processes=8):
+    """Oracle full runs of sorted ids; records come back in id order."""
+    which = _inst_of(wl, ids)
+    per = [ids[which == k] for k in range(len(wl.instances))]
+    recs, _ = orc.run_workload(wl, per, processes=processes)
+    return recs, np.concatenate([p for p in per if len(p)])
+
+
+def _upload_final(Q, torch, ctx, recs):
+    n = len(recs)
+    st = ctx.new_state(n)
+    d = np.zeros((Q.NF, n))
+    d[:12] = recs["y"].T
+    d[Q.F_T] = recs["t"]
+    d[Q.F_TMAX] = recs["tmax"]
+    d[Q.F_RSTOP] = recs["rstop"]
+    d[Q.F_E0] = recs["e0"]
+    d[Q.F_ESCALE] = recs["escale"]
+    st.d.copy_(torch.as_tensor(d))
+    st.status.copy_(torch.as_tensor(recs["status"].astype(np.uint8)))
+    return st
+
+
+def test_classify_same_final_state(Q, torch, orc):
+    """Labels and (v_t, j_t) bins bit-exact when both sides get the same final
+    state; v', j', W to rounding.  A flip is tolerated only when the oracle's
+    v' + 1/2 lies within 1e-10 of a bin edge."""
+    wl = W.config_batched()
+    # energetic instances (reaction / dissociation open) and a few slow ones
+    ks = [k for k, I in enumerate(wl.instances) if I.Ec_K > 3e4] + [0, 7]
+    rng = np.random.default_rng(11)
+    ids = np.sort(np.concatenate([wl.instances[k].first_id + rng.choice(1042, 4, replace=False)
+                                  for k in ks]))
+    recs, ids = _oracle_final_states(orc, wl, ids)
+    ctx = _ctx(Q, wl)
+    st = _upload_final(Q, torch, ctx, recs)
+    out = ctx.new_outcome(len(recs))
+    ctx.classify(st, out)
+    torch.cuda.synchronize()
+    lab = out.label.cpu().numpy()
+    vt = out.vt.cpu().numpy()
+    jt = out.jt.cpu().numpy()
+    od = out.d.cpu().numpy()
+    flips = 0
+    for c, r in enumerate(recs):
+        if (lab[c], vt[c], jt[c]) != (r["label"], r["vt"], r["jt"]):
+            margin = abs((r["vprime"] + 0.5) - round(r["vprime"] + 0.5))
+            assert lab[c] == r["label"] and margin < 1e-10, (c, lab[c], r["label"])
+            flips += 1
+        if r["label"] <= 2:
+            assert od[0, c] == pytest.approx(r["vprime"], abs=1e-9)
+            assert od[1, c] == pytest.approx(r["jprime"], abs=1e-9)
+            assert od[2, c] == pytest.approx(r["wgb"], rel=1e-6, abs=1e-9)
+        assert od[3, c] == pytest.approx(r["dE_rel"], abs=1e-12)
+    assert flips == 0
+    labels = np.bincount(lab, minlength=6)
+    print("labels of the shared final states:", labels)
+    assert labels[Q.QUENCH] > 0 and labels[Q.R1] + labels[Q.R2] > 0 and labels[Q.DISS] > 0
+    # the same labels give the same cross sections
+    tid = torch.as_tensor(ids, device="cuda:0")
+    xs, hist = ctx.cross_sections(out, tid)
+    xs = xs.cpu().numpy()
+    ref = orc.cross_sections(wl, recs["label"], np.ones(len(recs)), _inst_of(wl, ids))
+    sel = [k for k in range(len(wl.instances)) if ref["counts"][k].sum() > 0]
+    assert np.array_equal(xs[sel, 1:7], ref["counts"][sel].astype(float))
+    assert np.allclose(xs[sel, 7:11], ref["P"][sel], rtol=1e-14, atol=0)
+    assert np.allclose(xs[sel, 11:15], ref["dP"][sel], rtol=1e-12, atol=1e-15)
+    assert np.allclose(xs[sel, 15:19], ref["sigma"][sel], rtol=1e-14, atol=0)
+    assert np.allclose(xs[sel, 23:27], ref["rate"][sel], rtol=1e-13, atol=0)
+    H, Wt = orc.gb_distributions(wl, recs["label"], recs["vt"], recs["wgb"], _inst_of(wl, ids),
+                                 vmax=Q.VMAX)
+    assert np.allclose(hist.cpu().numpy()[sel], H[sel], rtol=1e-6, atol=1e-9)
+    assert np.allclose(xs[sel, Q.XS_WTOT], Wt[sel], rtol=1e-6, atol=1e-9)
+
+
+def test_cross_sections_statistical(Q, torch, orc):
+    """Independent full runs (GPU vs oracle, same seeds): per-channel cross
+    sections agree within 3 combined standard errors."""
+    inst = [W.Instance(5.0e4, 4, 0, 1200, 0, 4242, W.B_AREA, 0.0, 6.0)]
+    wl = W.Workload("stat", W.h2ca_system(), W.Params(), inst)
+    ctx = _ctx(Q, wl)
+    tid = ctx.all_ids()
+    n = tid.numel()
+    st = ctx.new_state(n)
+    ctx.init_conditions(tid, st)
+    ctx.propagate(st)
+    out = ctx.new_outcome(n)
+    ctx.classify(st, out)
+    xs, _ = ctx.cross_sections(out, tid)
+    xs = xs.cpu().numpy()[0]
+    recs, which = orc.run_workload(wl, processes=8)
+    ref = orc.cross_sections(wl, recs["label"], np.ones(len(recs)), which)
+    assert xs[0] == n
+    for c in range(4):
+        s_g, e_g = xs[15 + c], xs[19 + c]
+        s_o, e_o = ref["sigma"][0, c], ref["dsigma"][0, c]
+        comb = math.sqrt(e_g ** 2 + e_o ** 2)
+        assert abs(s_g - s_o) <= 3 * comb + 1e-12, (c, s_g, s_o, comb)
+    print("sigma GPU", xs[15:19], "oracle", ref["sigma"][0])
+    # energy gate on every finished trajectory
+    dE = out.d[3].cpu().numpy()
+    ok = (out.label.cpu().numpy() != Q.FAILED)
+    assert np.all(np.abs(dE[ok]) < 1e-8)
+
+
+# ----------------------------------------------------------------------------
+def test_empty_and_single(Q, torch):
+    wl = W.config_small(n_traj=5)
+    ctx = _ctx(Q, wl)
+    tid = torch.zeros(0, dtype=torch.int64, device="cuda:0")
+    st = ctx.new_state(1)
+    ctx.init_conditions(tid, st)
+    ctx.propagate(st, n=0)
+    out = ctx.new_outcome(1)
+    ctx.classify(st, out, n=0)
+    xs, _ = ctx.cross_sections(out, tid, n=0)
+    assert xs[0, 0].item() == 0.0
+    tid = torch.tensor([2], dtype=torch.int64, device="cuda:0")
+    ctx.init_conditions(tid, st)
+    ctx.propagate(st)
+    ctx.classify(st, out)
+    xs, _ = ctx.cross_sections(out, tid)
+    torch.cuda.synchronize()
+    assert xs[0, 0].item() == 1.0 and st.status.item() in (Q.OK_RSTOP, Q.OK_TMAX)
+
+
+def test_max_steps_and_idempotent_propagate(Q, torch, orc):
+    wl = W.config_small(n_traj=8)
+    ctx = _ctx(Q, wl, max_steps=5)
+    tid, st, smp = _gpu_init(Q, torch, ctx, list(range(8)))
+    ctx.propagate(st)
+    torch.cuda.synchronize()
+    assert st.status.cpu().tolist() == [Q.FAIL_MAXSTEPS] * 8
+    assert st.nstep.cpu().tolist() == [5] * 8
+    before = st.d.clone()
+    ctx.propagate(st)        # stopped trajectories are untouched
+    torch.cuda.synchronize()
+    assert torch.equal(before, st.d)
+    out = ctx.new_outcome(8)
+    ctx.classify(st, out)
+    torch.cuda.synchronize()
+    assert out.label.cpu().tolist() == [Q.FAILED] * 8
+    # the oracle fails the same way after the same 5 steps
+    sys, prm = orc.make_system(wl.system), orc.make_params(dataclasses.replace(wl.params, max_steps=5))
+    lev = orc.level(sys, 0, 0)
+    y0, aux, _ = orc.init(sys, prm, orc.make_instance(wl.instances[0]), lev, 3)
+    so, y, a, ns, nr = orc.propagate(sys, prm, y0, aux)
+    assert so == Q.FAIL_MAXSTEPS and ns == 5
+    assert np.allclose(st.d[:12, 3].cpu().numpy(), y, rtol=1e-12, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------
+def test_full_size_batched_properties(Q, torch, orc):
+    """The 100,032-trajectory batched workload at full size: sampled
+    trajectories checked one by one against the oracle (initial draws and
+    classification of the GPU's own final state) and properties that hold at
+    any size (counts, probabilities, energy gate)."""
+    wl = W.config_batched()
+    ctx = _ctx(Q, wl)
+    tid = ctx.all_ids()
+    n = tid.numel()
+    assert n == 100032
+    st = ctx.new_state(n)
+    smp = torch.zeros((Q.NS, n), dtype=torch.float64, device="cuda:0")
+    ctx.init_conditions(tid, st, smp)
+    ctx.propagate(st)
+    out = ctx.new_outcome(n)
+    ctx.classify(st, out)
+    xs, hist = ctx.cross_sections(out, tid)
+    torch.cuda.synchronize()
+    status = st.status.cpu().numpy()
+    assert np.all(status != Q.RUNNING)
+    lab = out.label.cpu().numpy()
+    xs = xs.cpu().numpy()
+    assert np.array_equal(xs[:, 0], [I.n_traj for I in wl.instances])
+    assert np.array_equal(xs[:, 1:7].sum(axis=1), xs[:, 0])
+    P = xs[:, 7:11]
+    assert np.all(P >= 0) and np.all(P.sum(axis=1) <= 1 + 1e-12)
+    dE = out.d[3].cpu().numpy()
+    fin = lab != Q.FAILED
+    assert fin.mean() > 0.999
+    assert np.all(np.abs(dE[fin]) < 1e-8), np.abs(dE[fin]).max()
+    # sampled one-by-one checks
+    rng = np.random.default_rng(3)
+    sample_idx = rng.choice(n, 48, replace=False)
+    sys, prm = orc.make_system(wl.system), orc.make_params(wl.params)
+    d = st.d.cpu().numpy()
+    s = smp.cpu().numpy()
+    vt = out.vt.cpu().numpy()
+    jt = out.jt.cpu().numpy()
+    which = _inst_of(wl, np.arange(n))
+    for c in sample_idx:
+        I = wl.instances[which[c]]
+        lev = orc.level(sys, I.v, I.j)
+        y0, aux, sm = orc.init(sys, prm, orc.make_instance(I), lev, int(c))
+        assert np.array_equal(s[:5, c], sm[:5])
+        if fin[c]:
+            r = orc.classify(sys, prm, d[:12, c])
+            assert (r["label"], r["vt"], r["jt"]) == (lab[c], vt[c], jt[c]), c
+    print("label totals", np.bincount(lab, minlength=6))
