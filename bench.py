@@ -125,7 +125,8 @@ def main():
     # work of the last step
     nstep = st.nstep.cpu().numpy().astype(np.int64)
     nrej = st.nrej.cpu().numpy().astype(np.int64)
-    trial_steps = int(nstep.sum() + nrej.sum())
+    per_traj = nstep + nrej
+    trial_steps = int(per_traj.sum())
     flops = trial_steps * F_STEP_MORSE
     achieved = flops / (prop_ms * 1e-3) / 1e12
     lab = out.label.cpu().numpy()
@@ -154,6 +155,9 @@ def main():
                      "kernel_ms": prop_ms, "trial_steps": trial_steps,
                      "flop_per_trial_step": F_STEP_MORSE},
         "trial_steps_per_s": trial_steps / (ms_step * 1e-3),
+        "trial_steps_per_traj": {q: int(np.percentile(per_traj, p)) for q, p in
+                                 (("p50", 50), ("p90", 90), ("p99", 99), ("p999", 99.9),
+                                  ("max", 100))},
         "max_abs_dE_rel": float(np.abs(dE[fin]).max()) if fin.any() else None,
         "labels": np.bincount(lab, minlength=6).tolist(),
         "wall_s": wall,

@@ -95,6 +95,73 @@ QD double ipow(double x, int n)
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// fast FP64 helpers for the inner loop (hardware estimates refined to full
+// double precision; a few ulp at most, which the parity bars absorb)
+// ---------------------------------------------------------------------------
+// 1/x: v_rcp_f64 estimate and two Newton steps y <- y (2 - x y)
+QD double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// sqrt(s) and 1/sqrt(s) for s > 0: v_rsq_f64 estimate and two coupled
+// Goldschmidt iterations (g -> sqrt(s), h -> 1/(2 sqrt(s))).
+QD void sqrt_rsqrt(double s, double& r, double& ir)
+{
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+    double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    r = g;
+    ir = h + h;
+}
+
+// e^x for x < 709: Cody-Waite reduction x = n ln2 + r, |r| <= ln2/2, with
+// ln2 split in a high part exact for |n| < 2^20 and a low correction, then
+// the Taylor series of e^r to degree 13 (truncation < 5e-18 relative) in
+// Horner form, scaled by 2^n.
+QD double exp_cw(double x)
+{
+    const double kLog2e = 1.4426950408889634074;
+    const double kLn2Hi = 6.93147180369123816490e-01;
+    const double kLn2Lo = 1.90821492927058770002e-10;
+    const double n = rint(x * kLog2e);
+    double r = fma(-n, kLn2Hi, x);
+    r = fma(-n, kLn2Lo, r);
+    double p = 1.0 / 6227020800.0;           // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);        // 1/12!
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
+// Step-size factor err^(-1/5) of the controller, in FP32 (a heuristic: its
+// value only shapes the step sequence, never the accuracy bound).
+QD double ctrl_pow(double err)
+{
+    const float l = __builtin_amdgcn_logf((float)err);   // log2
+    return (double)__builtin_amdgcn_exp2f(-0.2f * l);
+}
+
 QD void pot_morse(const Pot& P, double r, double& V, double& d1, double& d2)
 {
     const double De = P.p0, re = P.p1, a = P.p2;
@@ -146,14 +213,14 @@ QD double dV_over_r(const Pot& P, double r, double ir)
 {
     const int kind = K >= 0 ? K : P.kind;
     if (kind == MORSE) {
-        const double e = exp(-P.p2 * (r - P.p1));
-        return 2.0 * P.p0 * P.p2 * e * (1.0 - e) * ir;
+        const double e = exp_cw(P.p2 * (P.p1 - r));
+        return (2.0 * P.p0 * P.p2) * (e - e * e) * ir;
     } else if (kind == LJ) {
         const double tn = P.p0 * ipow(ir, P.n), tm = P.p1 * ipow(ir, P.m);
         return (-P.n * tn + P.m * tm) * ir * ir;
     } else {
         const double ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
-        return (-P.p1 * P.p0 * exp(-P.p1 * r) * ir) + 6.0 * P.p2 * ir6 * ir2;
+        return (-P.p1 * P.p0) * exp_cw(-P.p1 * r) * ir + (6.0 * P.p2) * ir6 * ir2;
     }
 }
 
@@ -178,16 +245,20 @@ QD void force(const Sys& S, const double* x, double* F, double* s2)
     const double sab = rab[0] * rab[0] + rab[1] * rab[1] + rab[2] * rab[2];
     const double sbc = rbc[0] * rbc[0] + rbc[1] * rbc[1] + rbc[2] * rbc[2];
     const double sca = rca[0] * rca[0] + rca[1] * rca[1] + rca[2] * rca[2];
-    const double dab = sqrt(sab), dbc = sqrt(sbc), dca = sqrt(sca);
-    const double gab = dV_over_r<K0>(S.pot[0], dab, 1.0 / dab);
-    const double gbc = dV_over_r<K1>(S.pot[1], dbc, 1.0 / dbc);
-    const double gca = dV_over_r<K2>(S.pot[2], dca, 1.0 / dca);
+    double dab, dbc, dca, iab, ibc, ica;
+    sqrt_rsqrt(sab, dab, iab);
+    sqrt_rsqrt(sbc, dbc, ibc);
+    sqrt_rsqrt(sca, dca, ica);
+    const double gab = dV_over_r<K0>(S.pot[0], dab, iab);
+    const double gbc = dV_over_r<K1>(S.pot[1], dbc, ibc);
+    const double gca = dV_over_r<K2>(S.pot[2], dca, ica);
+    const double cgbc = S.cA * gbc, cgca = S.cB * gca;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         // -dV/drho1 = -g_AB r_AB + cA g_BC r_BC + cB g_CA r_CA
-        F[a] = -gab * rab[a] + S.cA * gbc * rbc[a] + S.cB * gca * rca[a];
+        F[a] = fma(cgca, rca[a], fma(cgbc, rbc[a], -gab * rab[a]));
         // -dV/drho2 = -g_BC r_BC + g_CA r_CA
-        F[3 + a] = -gbc * rbc[a] + gca * rca[a];
+        F[3 + a] = fma(gca, rca[a], -gbc * rbc[a]);
     }
     s2[0] = sab;
     s2[1] = sbc;
@@ -276,50 +347,58 @@ QD double dopri5_trial(const Sys& S, const double* x, const double* p, const dou
                        double* F7, double* s2)
 {
     using namespace dp;
-    double v[6], X[6], F2[6], F3[6], F4[6], F5[6], F6[6], junk[3];
-    const double im[6] = {S.inv_mu12, S.inv_mu12, S.inv_mu12,
-                          S.inv_mu123, S.inv_mu123, S.inv_mu123};
+    double X[6], F2[6], F3[6], F4[6], F5[6], F6[6], junk[3];
     const double hh = h * h;
+    // per-component 1/mu (uniform) and h^2/mu
+    const double im0 = S.inv_mu12, im1 = S.inv_mu123;
+    const double g0 = hh * im0, g1 = hh * im1;
+#define IM(i) ((i) < 3 ? im0 : im1)
+#define GG(i) ((i) < 3 ? g0 : g1)
 #pragma unroll
-    for (int i = 0; i < 6; ++i) v[i] = p[i] * im[i];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) X[i] = x[i] + (h * c2) * v[i];
+    for (int i = 0; i < 6; ++i) X[i] = fma(h * c2 * IM(i), p[i], x[i]);
     force<K0, K1, K2>(S, X, F2, junk);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) X[i] = x[i] + (h * c3) * v[i] + hh * im[i] * (q31 * F1[i]);
+    for (int i = 0; i < 6; ++i)
+        X[i] = fma(GG(i), q31 * F1[i], fma(h * c3 * IM(i), p[i], x[i]));
     force<K0, K1, K2>(S, X, F3, junk);
 #pragma unroll
     for (int i = 0; i < 6; ++i)
-        X[i] = x[i] + (h * c4) * v[i] + hh * im[i] * (q41 * F1[i] + q42 * F2[i]);
+        X[i] = fma(GG(i), fma(q42, F2[i], q41 * F1[i]), fma(h * c4 * IM(i), p[i], x[i]));
     force<K0, K1, K2>(S, X, F4, junk);
 #pragma unroll
     for (int i = 0; i < 6; ++i)
-        X[i] = x[i] + (h * c5) * v[i] + hh * im[i] * (q51 * F1[i] + q52 * F2[i] + q53 * F3[i]);
+        X[i] = fma(GG(i), fma(q53, F3[i], fma(q52, F2[i], q51 * F1[i])),
+                   fma(h * c5 * IM(i), p[i], x[i]));
     force<K0, K1, K2>(S, X, F5, junk);
 #pragma unroll
     for (int i = 0; i < 6; ++i)
-        X[i] = x[i] + h * v[i] +
-               hh * im[i] * (q61 * F1[i] + q62 * F2[i] + q63 * F3[i] + q64 * F4[i]);
+        X[i] = fma(GG(i), fma(q64, F4[i], fma(q63, F3[i], fma(q62, F2[i], q61 * F1[i]))),
+                   fma(h * IM(i), p[i], x[i]));
     force<K0, K1, K2>(S, X, F6, junk);
+    // step and error estimate (all but the F7 term) before the last force,
+    // so that F2..F6 are dead when F7 is evaluated
+    double ep[6], ex[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        xn[i] = x[i] + h * v[i] +
-                hh * im[i] * (w1 * F1[i] + w2 * F2[i] + w3 * F3[i] + w4 * F4[i] + w5 * F5[i]);
-        pn[i] = p[i] + h * (b1 * F1[i] + b3 * F3[i] + b4 * F4[i] + b5 * F5[i] + b6 * F6[i]);
+        xn[i] = fma(GG(i), fma(w5, F5[i], fma(w4, F4[i], fma(w3, F3[i], fma(w2, F2[i], w1 * F1[i])))),
+                    fma(h * IM(i), p[i], x[i]));
+        pn[i] = fma(h, fma(b6, F6[i], fma(b5, F5[i], fma(b4, F4[i], fma(b3, F3[i], b1 * F1[i])))),
+                    p[i]);
+        ex[i] = GG(i) * fma(z6, F6[i], fma(z5, F5[i], fma(z4, F4[i],
+                            fma(z3, F3[i], fma(z2, F2[i], z1 * F1[i])))));
+        ep[i] = fma(e6, F6[i], fma(e5, F5[i], fma(e4, F4[i], fma(e3, F3[i], e1 * F1[i]))));
     }
+#undef IM
+#undef GG
     force<K0, K1, K2>(S, xn, F7, s2);
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        const double ex = hh * im[i] *
-                          (z1 * F1[i] + z2 * F2[i] + z3 * F3[i] + z4 * F4[i] + z5 * F5[i] +
-                           z6 * F6[i]);
-        const double ep = h * (e1 * F1[i] + e3 * F3[i] + e4 * F4[i] + e5 * F5[i] + e6 * F6[i] +
-                               e7 * F7[i]);
-        const double sx = atol + rtol * fmax(fabs(x[i]), fabs(xn[i]));
-        const double sp = atol + rtol * fmax(fabs(p[i]), fabs(pn[i]));
-        const double qx = ex / sx, qp = ep / sp;
-        acc += qx * qx + qp * qp;
+        const double epi = h * fma(e7, F7[i], ep[i]);
+        const double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
+        const double sp = fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol);
+        const double qx = ex[i] * rcp_nr(sx), qp = epi * rcp_nr(sp);
+        acc = fma(qx, qx, fma(qp, qp, acc));
     }
     return sqrt(acc * (1.0 / 12.0));
 }
@@ -405,14 +484,14 @@ QD void lane_step(const Sys& S, const Prm& P, Lane& L)
         else if (m2 > L.rstop2) L.status = OK_RSTOP;
         else if (L.t >= L.tmax) L.status = OK_TMAX;
         if (!P.fixed_step) {
-            double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(err, -0.2)));
+            double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * ctrl_pow(err)));
             if (L.last_rej && fac > 1.0) fac = 1.0;
             L.h = hs * fac;
         }
         L.last_rej = 0;
     } else {
         L.nrej += 1;
-        L.h = hs * fmax(0.2, 0.9 * pow(err, -0.2));
+        L.h = hs * fmax(0.2, 0.9 * ctrl_pow(err));
         L.last_rej = 1;
     }
     if (L.status == RUNNING && !P.fixed_step && L.h < 1e-12 * L.tmax) L.status = FAIL_HMIN;
