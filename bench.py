@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 # FP64 operations per RK5(4) trial step of one trajectory on the all-Morse
 # surface (FMA = 2), counted from the propagation kernel's instruction
 # stream; see the measurement section of the design notes.
-F_STEP_MORSE = 2224.0
+F_STEP_MORSE = 1969.4
 PEAK_FP64_VECTOR = 78.6e12   # MI355X, FLOP/s
 
 
@@ -42,6 +42,15 @@ def parse():
                     help="CPU baseline runs every k-th trajectory id through the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-procs", type=int, default=16)
+    ap.add_argument("--path", default="run", choices=["run", "unfused"],
+                    help="run: fused persistent launch (qcams_run); unfused: the four ABI calls")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick run options with qcams_autotune before timing")
+    ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--refill-min", type=int, default=1)
+    ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--no-lpt", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     return ap.parse_args()
 
 
@@ -82,45 +91,60 @@ def main():
     dev = torch.device("cuda", 0)
     ctx = Q.Context(wl.system, wl.params, device=0)
     ctx.set_instances(wl.instances)
-    ids = ctx.all_ids()
+    stream = torch.cuda.Stream()
+    opts = Q.RunOpts(blocks=args.blocks, refill_min=args.refill_min,
+                     check_every=args.check_every, lpt=0 if args.no_lpt else 1,
+                     graph=0 if args.no_graph else 1)
+    tuned = None
+    with torch.cuda.stream(stream):
+        buf = ctx.new_run_buffers()
+        if args.autotune:
+            best, best_ms = ctx.autotune(buf, reps=1)
+            best.graph = opts.graph
+            opts = best
+            tuned = {"opts": best.as_dict(), "ms": best_ms}
+        ids = ctx.all_ids()
     n = ids.numel()
-    st = ctx.new_state(n)
-    out = ctx.new_outcome(n)
-    smp = torch.zeros((Q.NS, n), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
+    st, out = buf["state"], buf["outcome"]
     prop_times = []
 
     def step(timed):
-        ctx.set_instances(wl.instances)          # units, levels (a1, a2)
-        ctx.init_conditions(ids, st, smp)        # a3
-        if timed:
+        # units and levels of every instance (a1, a2), then the path (a3-a9)
+        ctx.set_instances(wl.instances)
+        if args.path == "run":
+            ctx.run(buf, opts, stream=stream)
+        else:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
+            ctx.init_conditions(ids, st, buf["sample"], stream=stream)
             e0.record(stream)
-        ctx.propagate(st)                        # a4, a5
-        if timed:
+            ctx.propagate(st, stream=stream)
             e1.record(stream)
-            prop_times.append((e0, e1))
-        ctx.classify(st, out)                    # a6
-        xs, hist = ctx.cross_sections(out, ids)  # a7, a8
-        return xs
+            ctx.classify(st, out, stream=stream)
+            ctx.cross_sections(out, ids, stream=stream)
+        if timed:
+            # duration of the propagation kernel: HIP events on its stream
+            prop_times.append(ctx.last_run_kernel_ms() if args.path == "run"
+                              else (e0, e1))
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        xs = step(True)
-        print("step done", file=sys.stderr, flush=True)
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step(True)
+            print("step done", file=sys.stderr, flush=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
-    prop_ms = float(np.mean([a.elapsed_time(b) for a, b in prop_times]))
+    prop_ms = float(np.mean([t if isinstance(t, float) else t[0].elapsed_time(t[1])
+                             for t in prop_times]))
 
     # work of the last step
     nstep = st.nstep.cpu().numpy().astype(np.int64)
@@ -151,9 +175,11 @@ def main():
                    "r_stop": wl.params.r_stop},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_FP64_VECTOR,
-                     "traffic": None, "kernel": "k_propagate<0,0,0>",
-                     "kernel_ms": prop_ms, "trial_steps": trial_steps,
+                     "traffic": None,
+                     "kernel": "k_persistent<0,0,0>" if args.path == "run" else "k_propagate<0,0,0>",
+                     "timed_ms": prop_ms, "trial_steps": trial_steps,
                      "flop_per_trial_step": F_STEP_MORSE},
+        "path": args.path, "run_opts": opts.as_dict(), "autotune": tuned,
         "trial_steps_per_s": trial_steps / (ms_step * 1e-3),
         "trial_steps_per_traj": {q: int(np.percentile(per_traj, p)) for q, p in
                                  (("p50", 50), ("p90", 90), ("p99", 99), ("p999", 99.9),

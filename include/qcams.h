@@ -216,6 +216,47 @@ int qcams_cross_sections(qcams_ctx *ctx, const qcams_outcome *out, const int64_t
                          const double *weight, int64_t n, double *xs, double *hist,
                          void *stream);
 
+/* Options of the fused persistent run. */
+typedef struct {
+    int32_t blocks;      /* persistent grid in 256-thread workgroups; 0 = 2 per compute unit */
+    int32_t refill_min;  /* refill a wave once this many of its 64 lanes are idle (1..64; 0 = 1) */
+    int32_t check_every; /* trial steps between refill checks (0 = 1) */
+    int32_t lpt;         /* 1: start instances longest-expected-first (cost ~ 1/(v_c tau_vj)) */
+    int32_t graph;       /* 1: capture the launch sequence once per buffer set and replay it */
+    int32_t pad;
+} qcams_run_opts;
+
+/* The whole hot path over every installed trajectory (N = sum of n_traj):
+ * initial conditions, propagation in one persistent launch whose lanes take
+ * a new trajectory as soon as theirs stops, classification, and the
+ * per-instance reduction of qcams_cross_sections.  Results are stored at
+ * each trajectory's natural position p (instances in id order, ids
+ * consecutive inside an instance): st, sample (may be NULL), out, and
+ * ids[p] (device int64 [N], written) as the matching trajectory id.  xs,
+ * hist (may be NULL) as in qcams_cross_sections.  opts may be NULL
+ * (defaults).  With opts->graph the launch sequence is captured into a HIP
+ * graph on first use (per buffer set and options) and replayed afterwards;
+ * calling qcams_set_instances invalidates it.  async.  Errors: EINVAL,
+ * ENOMEM, EHIP. */
+int qcams_run(qcams_ctx *ctx, const qcams_run_opts *opts, const qcams_state *st, double *sample,
+              const qcams_outcome *out, int64_t *ids, double *xs, double *hist, void *stream);
+
+/* Duration in milliseconds of the persistent propagation kernel of the last
+ * qcams_run on this context, from HIP events recorded around that launch on
+ * the run's stream (also when the run was a graph replay).  Waits for the
+ * run to finish.  sync.  Errors: EINVAL (no run yet), EHIP. */
+int qcams_last_run_kernel_ms(qcams_ctx *ctx, double *ms);
+
+/* Time qcams_run over a grid of options (grid 1/2/4 workgroups per CU,
+ * refill_min 1/8/32, check_every 1/8, instance order LPT / natural) on the
+ * installed instances -- install a calibration subset first -- and return
+ * the fastest in *best (graph off) with its time in *best_ms (may be NULL).
+ * Buffers as for qcams_run; each option is run `reps` times and the minimum
+ * kept.  sync.  Errors as qcams_run. */
+
+int qcams_autotune(qcams_ctx *ctx, const qcams_state *st, const qcams_outcome *out, int64_t *ids,
+                   double *xs, int32_t reps, qcams_run_opts *best, double *best_ms);
+
 #ifdef __cplusplus
 }
 #endif

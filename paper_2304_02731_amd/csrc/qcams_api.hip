@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/qcams.h"
@@ -23,7 +24,24 @@ struct qcams_ctx {
     int kinds = 0;               // kind triple packed as k0 + 3 k1 + 9 k2
     Inst* d_inst = nullptr;      // device instance table
     int32_t n_inst = 0;
+    int32_t inst_cap = 0;        // capacity of the device instance tables
     std::vector<Inst> h_inst;
+    int64_t n_total = 0;          // sum of n_traj
+    int32_t* d_id_inst = nullptr;    // [n_inst] identity order
+    // longest-expected-first order of the instances for the persistent run
+    int32_t* d_lpt_inst = nullptr;   // [n_inst] instance index by LPT rank
+    int64_t* d_lpt_off = nullptr;    // [n_inst + 1] work offsets in LPT order
+    int64_t* d_nat_off = nullptr;    // [n_inst + 1] natural (id-sorted) offsets
+    unsigned long long* d_counter = nullptr;   // work counter of the persistent run
+    int64_t* d_order = nullptr;                // [n_total] work item -> natural position
+    int64_t order_cap = 0;
+    hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
+    int n_cu = 0;
+    // captured launch sequence of qcams_run
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    uint64_t graph_key[16] = {0};
     char err[512] = {0};
 };
 
@@ -85,16 +103,17 @@ __device__ inline int find_instance(const Inst* inst, int n_inst, int64_t id)
     return k;
 }
 
-__global__ void k_init(Sys S, Prm P, const Inst* inst, int n_inst, const int64_t* ids,
-                       int64_t n, double* d, int32_t* nstep, int32_t* nrej, uint8_t* status,
-                       int64_t ld, double* sample)
+template <int K0, int K1, int K2>
+__global__ void __launch_bounds__(256)
+k_init(Sys S, Prm P, const Inst* inst, int n_inst, const int64_t* ids, int64_t n, double* d,
+       int32_t* nstep, int32_t* nrej, uint8_t* status, int64_t ld, double* sample)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t id = ids[i];
     const int k = find_instance(inst, n_inst, id);
     double x[6] = {0, 0, 0, 0, 0, 0}, p[6] = {0, 0, 0, 0, 0, 0}, smp[5] = {0, 0, 0, 0, 0};
-    double tmax = 0.0, rstop = 0.0, e0 = 0.0, esc = 1.0;
+    double tmax = 0.0, rstop = 0.0, e0 = 0.0, esc = 1.0, h = 0.0;
     uint8_t st = RUNNING;
     if (k < 0) {
         st = FAIL_NONFINITE;
@@ -103,6 +122,12 @@ __global__ void k_init(Sys S, Prm P, const Inst* inst, int n_inst, const int64_t
         if (!initial_state(S, P, I, id, x, p, tmax, rstop, smp)) st = FAIL_NONFINITE;
         e0 = hamiltonian(S, x, p);
         esc = fmax(fabs(e0), fabs(I.Evj));
+        // starting step of the RK5(4) controller (fixed step: h_fixed)
+        if (st == RUNNING) {
+            double F[6], s2[3];
+            force<K0, K1, K2>(S, x, F, s2);
+            h = P.fixed_step ? P.h_fixed : initial_step<K0, K1, K2>(S, x, p, F, P.atol, P.rtol, tmax);
+        }
     }
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
@@ -114,7 +139,7 @@ __global__ void k_init(Sys S, Prm P, const Inst* inst, int n_inst, const int64_t
     d[QCAMS_F_RSTOP * ld + i] = rstop;
     d[QCAMS_F_E0 * ld + i] = e0;
     d[QCAMS_F_ESCALE * ld + i] = esc;
-    d[QCAMS_F_H * ld + i] = 0.0;
+    d[QCAMS_F_H * ld + i] = h;
     nstep[i] = 0;
     nrej[i] = 0;
     status[i] = st;
@@ -169,6 +194,122 @@ __global__ void __launch_bounds__(256) k_propagate(Sys S, Prm P, double* d, int3
     nstep[i] = L.nstep;
     nrej[i] = L.nrej;
     status[i] = (uint8_t)L.status;
+}
+
+// ---------------------------------------------------------------------------
+// persistent propagation with lane refill
+//
+// Work items w = 0..N-1 are trajectories in longest-expected-first instance
+// order.  Each lane holds one trajectory; when at least `refill_min` lanes of
+// a wave are idle, lane 0 claims that many items with one atomic add and the
+// idle lanes take consecutive items by their rank among the idle lanes
+// (ballot + mbcnt).  A lane picks up its trajectory's initial state (drawn
+// beforehand by the initial-condition kernel) and writes the final state back
+// to the same natural position (instances in id order), where classification
+// and reduction read them.
+// ---------------------------------------------------------------------------
+__global__ void k_reset_counter(unsigned long long* c) { *c = 0ull; }
+
+struct RunMap {
+    const int64_t* order;   // work item -> natural position
+    int64_t N;
+};
+
+// natural positions and ids of the installed instances, and the work order
+// (instances longest-expected-first, or in id order)
+__global__ void k_run_tables(const Inst* inst, int n_inst, const int32_t* ord_inst,
+                             const int64_t* ord_off, const int64_t* nat_off, int64_t n,
+                             int64_t* ids, int64_t* order)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n) return;
+    int lo = 0, hi = n_inst - 1, j = 0;
+    while (lo <= hi) {   // last rank with ord_off <= w
+        const int mid = (lo + hi) >> 1;
+        if (ord_off[mid] <= w) { j = mid; lo = mid + 1; }
+        else hi = mid - 1;
+    }
+    const int k = ord_inst[j];
+    const int64_t local = w - ord_off[j];
+    const int64_t pos = nat_off[k] + local;
+    order[w] = pos;
+    ids[pos] = inst[k].first_id + local;
+}
+
+template <int K0, int K1, int K2>
+__global__ void __launch_bounds__(256)
+k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min, int check_every,
+             double* d, int32_t* nstep, int32_t* nrej, uint8_t* status, int64_t ld)
+{
+    const unsigned lane = __lane_id();
+    const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    Lane L;
+    int64_t pos = -1;
+    bool active = false;
+    bool exhausted = false;
+    L.status = RUNNING;
+    for (;;) {
+        // ---- refill (wave-uniform) ----
+        const unsigned long long idle = __ballot(!active);
+        const int nidle = __popcll(idle);
+        const bool none_active = nidle == 64;
+        if (!exhausted && (nidle >= refill_min || (none_active && nidle > 0))) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(counter, (unsigned long long)nidle);
+            const unsigned lo32 = __builtin_amdgcn_readfirstlane((unsigned)(base & 0xffffffffull));
+            const unsigned hi32 = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
+            base = ((unsigned long long)hi32 << 32) | lo32;
+            if (base + (unsigned long long)nidle >= (unsigned long long)M.N) exhausted = true;
+            if (!active) {
+                const int64_t w = (int64_t)base + __popcll(idle & lt_mask);
+                if (w < M.N) {
+                    pos = M.order[w];
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) {
+                        L.x[f] = d[f * ld + pos];
+                        L.p[f] = d[(6 + f) * ld + pos];
+                    }
+                    L.t = d[QCAMS_F_T * ld + pos];
+                    L.tmax = d[QCAMS_F_TMAX * ld + pos];
+                    const double rs = d[QCAMS_F_RSTOP * ld + pos];
+                    L.rstop2 = rs * rs;
+                    L.h = d[QCAMS_F_H * ld + pos];
+                    L.nstep = nstep[pos];
+                    L.nrej = nrej[pos];
+                    L.last_rej = 0;
+                    L.status = status[pos];
+                    if (L.status == RUNNING) {
+                        double s2[3];
+                        force<K0, K1, K2>(S, L.x, L.F, s2);
+                        if (!is_finite(L.t) || !is_finite(L.tmax) || !is_finite(L.h)) L.status = FAIL_NONFINITE;
+                        else if (L.t >= L.tmax) L.status = OK_TMAX;
+                        else if (L.nstep >= P.max_steps) L.status = FAIL_MAXSTEPS;
+                    }
+                    active = true;
+                }
+            }
+        }
+        if (__ballot(active) == 0ull) break;
+        // ---- integrate ----
+        for (int s = 0; s < check_every; ++s) {
+            if (active && L.status == RUNNING) lane_step<K0, K1, K2>(S, P, L);
+        }
+        // ---- retire finished lanes ----
+        if (active && L.status != RUNNING) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                d[f * ld + pos] = L.x[f];
+                d[(6 + f) * ld + pos] = L.p[f];
+            }
+            d[QCAMS_F_T * ld + pos] = L.t;
+            d[QCAMS_F_H * ld + pos] = L.h;
+            nstep[pos] = L.nstep;
+            nrej[pos] = L.nrej;
+            status[pos] = (uint8_t)L.status;
+            active = false;
+            L.status = RUNNING;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -337,6 +478,33 @@ static void launch_propagate(qcams_ctx* c, const qcams_state* st, int64_t n, hip
                        c->prm, st->d, st->nstep, st->nrej, st->status, st->ld, n);
 }
 
+template <int K0, int K1, int K2>
+static void launch_persistent(qcams_ctx* c, int blocks, int refill_min, int check_every,
+                              const int64_t* order, const qcams_state* st, hipStream_t s)
+{
+    RunMap M{order, c->n_total};
+    hipLaunchKernelGGL((k_persistent<K0, K1, K2>), dim3(blocks), dim3(256), 0, s, c->sys, c->prm,
+                       M, c->d_counter, refill_min, check_every, st->d, st->nstep, st->nrej,
+                       st->status, st->ld);
+}
+
+template <int K0, int K1, int K2>
+static void launch_init(qcams_ctx* c, const int64_t* ids, int64_t n, const qcams_state* st,
+                        double* sample, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_init<K0, K1, K2>), dim3(grid_of(n, 256)), dim3(256), 0, s, c->sys, c->prm,
+                       c->d_inst, c->n_inst, ids, n, st->d, st->nstep, st->nrej, st->status,
+                       st->ld, sample);
+}
+
+static void dispatch_init(qcams_ctx* c, const int64_t* ids, int64_t n, const qcams_state* st,
+                          double* sample, hipStream_t s)
+{
+    if (c->kinds == 0) launch_init<0, 0, 0>(c, ids, n, st, sample, s);
+    else if (c->kinds == QCAMS_LJ + 3 * QCAMS_MORSE + 9 * QCAMS_BUCK) launch_init<1, 0, 2>(c, ids, n, st, sample, s);
+    else launch_init<-1, -1, -1>(c, ids, n, st, sample, s);
+}
+
 extern "C" {
 
 int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qcams_params* prm)
@@ -442,7 +610,18 @@ void qcams_destroy(qcams_ctx* c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->d_inst) (void)hipFree(c->d_inst);
+    if (c->d_lpt_inst) (void)hipFree(c->d_lpt_inst);
+    if (c->d_id_inst) (void)hipFree(c->d_id_inst);
+    if (c->d_lpt_off) (void)hipFree(c->d_lpt_off);
+    if (c->d_nat_off) (void)hipFree(c->d_nat_off);
+    if (c->d_counter) (void)hipFree(c->d_counter);
+    if (c->d_order) (void)hipFree(c->d_order);
+    for (int e = 0; e < 2; ++e)
+        if (c->ev_prop[e]) (void)hipEventDestroy(c->ev_prop[e]);
     delete c;
 }
 
@@ -524,18 +703,50 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
         if (!(b < c->prm.R0)) return fail(c, QCAMS_EINVAL, "instance %d: impact parameter >= R0", k);
     }
     HIP_OK(c, hipSetDevice(c->device));
-    if (c->d_inst) {
-        HIP_OK(c, hipFree(c->d_inst));
+    // device tables are reused while they are large enough, so that a captured
+    // run (which reads them at replay time) stays valid
+    if (n_inst > c->inst_cap) {
+        for (void* q : {(void*)c->d_inst, (void*)c->d_lpt_inst, (void*)c->d_id_inst,
+                        (void*)c->d_lpt_off, (void*)c->d_nat_off})
+            if (q) (void)hipFree(q);
         c->d_inst = nullptr;
-    }
-    if (hipMalloc(&c->d_inst, n_inst * sizeof(Inst)) != hipSuccess) {
-        c->d_inst = nullptr;
+        c->d_lpt_inst = c->d_id_inst = nullptr;
+        c->d_lpt_off = c->d_nat_off = nullptr;
+        c->inst_cap = 0;
         c->n_inst = 0;
-        return fail(c, QCAMS_ENOMEM, "instance table allocation failed");
+        c->graph_key[0] = 0;
+        if (hipMalloc(&c->d_inst, n_inst * sizeof(Inst)) != hipSuccess ||
+            hipMalloc(&c->d_lpt_inst, n_inst * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->d_id_inst, n_inst * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->d_lpt_off, (n_inst + 1) * sizeof(int64_t)) != hipSuccess ||
+            hipMalloc(&c->d_nat_off, (n_inst + 1) * sizeof(int64_t)) != hipSuccess)
+            return fail(c, QCAMS_ENOMEM, "instance table allocation failed");
+        c->inst_cap = n_inst;
     }
     HIP_OK(c, hipMemcpy(c->d_inst, h.data(), n_inst * sizeof(Inst), hipMemcpyHostToDevice));
     c->n_inst = n_inst;
     c->h_inst = h;
+    // natural offsets and the longest-expected-first order: expected trial
+    // steps of a trajectory ~ collision time / vibrational period ~ 1/(v_c tau)
+    std::vector<int64_t> nat(n_inst + 1, 0), loff(n_inst + 1, 0);
+    for (int k = 0; k < n_inst; ++k) nat[k + 1] = nat[k] + h[k].n_traj;
+    std::vector<int32_t> order(n_inst);
+    std::vector<double> cost(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        order[k] = k;
+        const double vc = sqrt(2.0 * h[k].Ec * c->sys.inv_mu123);
+        cost[k] = 1.0 / (vc * h[k].tau);
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int r = 0; r < n_inst; ++r) loff[r + 1] = loff[r] + h[order[r]].n_traj;
+    std::vector<int32_t> ident(n_inst);
+    for (int k = 0; k < n_inst; ++k) ident[k] = k;
+    c->n_total = nat[n_inst];
+    HIP_OK(c, hipMemcpy(c->d_nat_off, nat.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_OK(c, hipMemcpy(c->d_lpt_off, loff.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_OK(c, hipMemcpy(c->d_lpt_inst, order.data(), n_inst * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_OK(c, hipMemcpy(c->d_id_inst, ident.data(), n_inst * sizeof(int32_t), hipMemcpyHostToDevice));
     return QCAMS_OK;
 }
 
@@ -556,9 +767,7 @@ int qcams_init_conditions(qcams_ctx* c, const int64_t* ids, int64_t n, const qca
     if (n == 0) return QCAMS_OK;
     if (!ids) return fail(c, QCAMS_EINVAL, "null ids");
     HIP_OK(c, hipSetDevice(c->device));
-    hipLaunchKernelGGL(k_init, dim3(grid_of(n, 256)), dim3(256), 0, (hipStream_t)stream, c->sys,
-                       c->prm, c->d_inst, c->n_inst, ids, n, st->d, st->nstep, st->nrej,
-                       st->status, st->ld, sample);
+    dispatch_init(c, ids, n, st, sample, (hipStream_t)stream);
     HIP_OK(c, hipGetLastError());
     return QCAMS_OK;
 }
@@ -605,6 +814,191 @@ int qcams_cross_sections(qcams_ctx* c, const qcams_outcome* out, const int64_t* 
                        c->d_inst, c->n_inst, c->sys.mu123, out->label, out->vt, out->d, out->ld,
                        ids, weight, n, xs, hist);
     HIP_OK(c, hipGetLastError());
+    return QCAMS_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// fused persistent run, launch-graph capture, autotuning
+// ---------------------------------------------------------------------------
+static int enqueue_run(qcams_ctx* c, const qcams_run_opts* o, const qcams_state* st,
+                       double* sample, const qcams_outcome* out, int64_t* ids, double* xs,
+                       double* hist, hipStream_t s)
+{
+    const int64_t n = c->n_total;
+    const bool lpt = o->lpt != 0;
+    int64_t* order = c->d_order;
+    hipLaunchKernelGGL(k_run_tables, dim3(grid_of(n, 256)), dim3(256), 0, s, c->d_inst, c->n_inst,
+                       lpt ? c->d_lpt_inst : c->d_id_inst, lpt ? c->d_lpt_off : c->d_nat_off,
+                       c->d_nat_off, n, ids, order);
+    dispatch_init(c, ids, n, st, sample, s);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, c->d_counter);
+    const int blocks = o->blocks > 0 ? o->blocks : 2 * c->n_cu;
+    const int rm = o->refill_min < 1 ? 1 : (o->refill_min > 64 ? 64 : o->refill_min);
+    const int ce = o->check_every < 1 ? 1 : o->check_every;
+    if (hipEventRecord(c->ev_prop[0], s) != hipSuccess) return QCAMS_EHIP;
+    if (c->kinds == 0) launch_persistent<0, 0, 0>(c, blocks, rm, ce, order, st, s);
+    else if (c->kinds == QCAMS_LJ + 3 * QCAMS_MORSE + 9 * QCAMS_BUCK)
+        launch_persistent<1, 0, 2>(c, blocks, rm, ce, order, st, s);
+    else launch_persistent<-1, -1, -1>(c, blocks, rm, ce, order, st, s);
+    if (hipEventRecord(c->ev_prop[1], s) != hipSuccess) return QCAMS_EHIP;
+    hipLaunchKernelGGL(k_classify, dim3(grid_of(n, 128)), dim3(128), 0, s, c->sys, c->prm, st->d,
+                       st->status, st->ld, n, out->label, out->vt, out->jt, out->d, out->ld);
+    hipLaunchKernelGGL(k_xsec, dim3(c->n_inst), dim3(kRedThreads), 0, s, c->d_inst, c->n_inst,
+                       c->sys.mu123, out->label, out->vt, out->d, out->ld, (const int64_t*)ids,
+                       (const double*)nullptr, n, xs, hist);
+    return hipGetLastError() == hipSuccess ? QCAMS_OK : QCAMS_EHIP;
+}
+
+int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, double* sample,
+              const qcams_outcome* out, int64_t* ids, double* xs, double* hist, void* stream)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    if (c->n_inst < 1) return fail(c, QCAMS_EINVAL, "no instances installed");
+    const int64_t n = c->n_total;
+    if (int rc = check_state(c, st, n)) return rc;
+    if (!out || !ids || !xs || (n > 0 && (!out->label || !out->vt || !out->jt || !out->d || out->ld < n)))
+        return fail(c, QCAMS_EINVAL, "outcome / ids / xs buffers missing or too small");
+    qcams_run_opts o{};
+    o.blocks = 0;
+    o.refill_min = 1;
+    o.check_every = 1;
+    o.lpt = 1;
+    o.graph = 0;
+    if (opts) o = *opts;
+    if (o.blocks < 0 || o.refill_min < 0 || o.check_every < 0)
+        return fail(c, QCAMS_EINVAL, "negative run option");
+    HIP_OK(c, hipSetDevice(c->device));
+    if (!c->d_counter) {
+        if (hipMalloc(&c->d_counter, sizeof(unsigned long long)) != hipSuccess) {
+            c->d_counter = nullptr;
+            return fail(c, QCAMS_ENOMEM, "work counter allocation failed");
+        }
+    }
+    if (c->n_cu == 0) {
+        int cu = 0;
+        HIP_OK(c, hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device));
+        c->n_cu = cu > 0 ? cu : 256;
+    }
+    for (int e = 0; e < 2; ++e)
+        if (!c->ev_prop[e]) HIP_OK(c, hipEventCreate(&c->ev_prop[e]));
+    if (c->order_cap < n) {
+        if (c->d_order) HIP_OK(c, hipFree(c->d_order));
+        c->d_order = nullptr;
+        c->order_cap = 0;
+        if (hipMalloc(&c->d_order, (size_t)(n > 0 ? n : 1) * sizeof(int64_t)) != hipSuccess) {
+            c->d_order = nullptr;
+            return fail(c, QCAMS_ENOMEM, "work order allocation failed");
+        }
+        c->order_cap = n;
+        c->graph_key[0] = 0;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!o.graph) {
+        if (enqueue_run(c, &o, st, sample, out, ids, xs, hist, s) != QCAMS_OK)
+            return fail(c, QCAMS_EHIP, "run launch: %s", hipGetErrorString(hipGetLastError()));
+        return QCAMS_OK;
+    }
+    // graph: capture once per (buffers, options), replay afterwards
+    const uint64_t key[16] = {1,
+                              (uint64_t)st->d, (uint64_t)st->nstep, (uint64_t)st->nrej,
+                              (uint64_t)st->status, (uint64_t)st->ld, (uint64_t)sample,
+                              (uint64_t)out->label, (uint64_t)out->d, (uint64_t)out->ld,
+                              (uint64_t)ids, (uint64_t)xs, (uint64_t)hist,
+                              (uint64_t)o.blocks | ((uint64_t)o.refill_min << 32),
+                              (uint64_t)o.check_every | ((uint64_t)o.lpt << 32),
+                              ((uint64_t)out->vt ^ ((uint64_t)out->jt << 1)) + 1315423911ull *
+                                  ((uint64_t)c->n_total ^ ((uint64_t)c->n_inst << 40))};
+    if (memcmp(key, c->graph_key, sizeof key) != 0) {
+        if (c->graph_exec) {
+            HIP_OK(c, hipGraphExecDestroy(c->graph_exec));
+            c->graph_exec = nullptr;
+        }
+        if (c->graph) {
+            HIP_OK(c, hipGraphDestroy(c->graph));
+            c->graph = nullptr;
+        }
+        if (!c->cap_stream) HIP_OK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIP_OK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_run(c, &o, st, sample, out, ids, xs, hist, c->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (rc != QCAMS_OK || e != hipSuccess)
+            return fail(c, QCAMS_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+        c->graph = g;
+        HIP_OK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+        memcpy(c->graph_key, key, sizeof key);
+    }
+    HIP_OK(c, hipGraphLaunch(c->graph_exec, s));
+    return QCAMS_OK;
+}
+
+int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out, int64_t* ids,
+                   double* xs, int32_t reps, qcams_run_opts* best, double* best_ms)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    if (!best) return fail(c, QCAMS_EINVAL, "null result");
+    if (reps < 1) reps = 1;
+    HIP_OK(c, hipSetDevice(c->device));
+    hipStream_t s = nullptr;
+    HIP_OK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(c, hipEventCreate(&e0));
+    HIP_OK(c, hipEventCreate(&e1));
+    double best_t = 1e300;
+    qcams_run_opts bo{};
+    int rc = QCAMS_OK;
+    if (c->n_cu == 0) {
+        int cu = 0;
+        HIP_OK(c, hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device));
+        c->n_cu = cu > 0 ? cu : 256;
+    }
+    const int blocks_c[3] = {c->n_cu, 2 * c->n_cu, 4 * c->n_cu};
+    const int refill_c[3] = {1, 8, 32};
+    const int check_c[2] = {1, 8};
+    for (int lpt = 1; lpt >= 0 && rc == QCAMS_OK; --lpt)
+        for (int bi = 0; bi < 3 && rc == QCAMS_OK; ++bi)
+            for (int ri = 0; ri < 3 && rc == QCAMS_OK; ++ri)
+                for (int ci = 0; ci < 2 && rc == QCAMS_OK; ++ci) {
+                    qcams_run_opts o{};
+                    o.blocks = blocks_c[bi];
+                    o.refill_min = refill_c[ri];
+                    o.check_every = check_c[ci];
+                    o.lpt = lpt;
+                    o.graph = 0;
+                    double tmin = 1e300;
+                    for (int r = 0; r < reps && rc == QCAMS_OK; ++r) {
+                        rc = hipEventRecord(e0, s) == hipSuccess ? QCAMS_OK : QCAMS_EHIP;
+                        if (rc == QCAMS_OK) rc = qcams_run(c, &o, st, nullptr, out, ids, xs, nullptr, s);
+                        if (rc == QCAMS_OK && hipEventRecord(e1, s) != hipSuccess) rc = QCAMS_EHIP;
+                        if (rc == QCAMS_OK && hipEventSynchronize(e1) != hipSuccess) rc = QCAMS_EHIP;
+                        float ms = 0.f;
+                        if (rc == QCAMS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = QCAMS_EHIP;
+                        if (rc == QCAMS_OK) tmin = fmin(tmin, (double)ms);
+                    }
+                    if (rc == QCAMS_OK && tmin < best_t) {
+                        best_t = tmin;
+                        bo = o;
+                    }
+                }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    if (rc != QCAMS_OK) return rc == QCAMS_EHIP ? fail(c, rc, "autotune run failed") : rc;
+    *best = bo;
+    if (best_ms) *best_ms = best_t;
+    return QCAMS_OK;
+}
+
+int qcams_last_run_kernel_ms(qcams_ctx* c, double* ms)
+{
+    if (!c || !ms) return fail(c, QCAMS_EINVAL, "null argument");
+    if (!c->ev_prop[0] || !c->ev_prop[1]) return fail(c, QCAMS_EINVAL, "no run recorded");
+    HIP_OK(c, hipSetDevice(c->device));
+    HIP_OK(c, hipEventSynchronize(c->ev_prop[1]));
+    float f = 0.f;
+    HIP_OK(c, hipEventElapsedTime(&f, c->ev_prop[0], c->ev_prop[1]));
+    *ms = (double)f;
     return QCAMS_OK;
 }
 

@@ -68,6 +68,14 @@ class StateC(C.Structure):
                 ("status", C.c_void_p), ("ld", C.c_int64)]
 
 
+class RunOpts(C.Structure):
+    _fields_ = [("blocks", C.c_int32), ("refill_min", C.c_int32), ("check_every", C.c_int32),
+                ("lpt", C.c_int32), ("graph", C.c_int32), ("pad", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
 class OutcomeC(C.Structure):
     _fields_ = [("label", C.c_void_p), ("vt", C.c_void_p), ("jt", C.c_void_p),
                 ("d", C.c_void_p), ("ld", C.c_int64)]
@@ -104,6 +112,11 @@ def lib():
     L.qcams_propagate.argtypes = [vp, C.POINTER(StateC), i64, vp]
     L.qcams_classify.argtypes = [vp, C.POINTER(StateC), i64, C.POINTER(OutcomeC), vp]
     L.qcams_cross_sections.argtypes = [vp, C.POINTER(OutcomeC), vp, vp, i64, vp, vp, vp]
+    L.qcams_run.argtypes = [vp, C.POINTER(RunOpts), C.POINTER(StateC), vp, C.POINTER(OutcomeC),
+                            vp, vp, vp, vp]
+    L.qcams_last_run_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
+    L.qcams_autotune.argtypes = [vp, C.POINTER(StateC), C.POINTER(OutcomeC), vp, vp, i32,
+                                 C.POINTER(RunOpts), C.POINTER(C.c_double)]
     for name in exported_names():
         getattr(L, name)  # raises if a declared symbol is missing
     _lib = L
@@ -302,6 +315,48 @@ class Context:
             hist.data_ptr() if hist is not None else None, _stream(stream)),
             "qcams_cross_sections")
         return xs, hist
+
+    @property
+    def n_total(self) -> int:
+        return sum(i.n_traj for i in self.instances)
+
+    def new_run_buffers(self):
+        """Buffers for qcams_run sized to the installed instances."""
+        import torch
+        n = self.n_total
+        dev = self.torch_device
+        return dict(state=self.new_state(n), outcome=self.new_outcome(n),
+                    sample=torch.zeros((NS, n), dtype=torch.float64, device=dev),
+                    ids=torch.zeros(n, dtype=torch.int64, device=dev),
+                    xs=torch.zeros((len(self.instances), XS_STRIDE), dtype=torch.float64, device=dev),
+                    hist=torch.zeros((len(self.instances), 3, VMAX), dtype=torch.float64, device=dev))
+
+    def run(self, buf, opts: Optional[RunOpts] = None, stream=None, with_sample=True,
+            with_hist=True):
+        """Fused persistent run of every installed trajectory (qcams_run)."""
+        st, out = buf["state"], buf["outcome"]
+        self._check(lib().qcams_run(
+            self._h, C.byref(opts) if opts is not None else None, C.byref(st.c()),
+            buf["sample"].data_ptr() if with_sample else None, C.byref(out.c()),
+            buf["ids"].data_ptr(), buf["xs"].data_ptr(),
+            buf["hist"].data_ptr() if with_hist else None, _stream(stream)), "qcams_run")
+        return buf["xs"], buf["hist"]
+
+    def last_run_kernel_ms(self) -> float:
+        """Duration of the persistent kernel of the last run (HIP events)."""
+        ms = C.c_double()
+        self._check(lib().qcams_last_run_kernel_ms(self._h, C.byref(ms)), "qcams_last_run_kernel_ms")
+        return ms.value
+
+    def autotune(self, buf, reps: int = 1):
+        """Fastest qcams_run options on the installed instances (qcams_autotune)."""
+        best = RunOpts()
+        ms = C.c_double()
+        self._check(lib().qcams_autotune(self._h, C.byref(buf["state"].c()),
+                                         C.byref(buf["outcome"].c()), buf["ids"].data_ptr(),
+                                         buf["xs"].data_ptr(), reps, C.byref(best), C.byref(ms)),
+                    "qcams_autotune")
+        return best, ms.value
 
     def all_ids(self):
         import torch
