@@ -48,7 +48,7 @@ def parse():
                     help="pick run options with qcams_autotune before timing")
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--refill-min", type=int, default=1)
-    ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-lpt", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     return ap.parse_args()

@@ -218,7 +218,7 @@ int qcams_cross_sections(qcams_ctx *ctx, const qcams_outcome *out, const int64_t
 
 /* Options of the fused persistent run. */
 typedef struct {
-    int32_t blocks;      /* persistent grid in 256-thread workgroups; 0 = 2 per compute unit */
+    int32_t blocks;      /* persistent grid in 256-thread workgroups; 0 = 1 per compute unit */
     int32_t refill_min;  /* refill a wave once this many of its 64 lanes are idle (1..64; 0 = 1) */
     int32_t check_every; /* trial steps between refill checks (0 = 1) */
     int32_t lpt;         /* 1: start instances longest-expected-first (cost ~ 1/(v_c tau_vj)) */
@@ -234,9 +234,11 @@ typedef struct {
  * consecutive inside an instance): st, sample (may be NULL), out, and
  * ids[p] (device int64 [N], written) as the matching trajectory id.  xs,
  * hist (may be NULL) as in qcams_cross_sections.  opts may be NULL
- * (defaults).  With opts->graph the launch sequence is captured into a HIP
- * graph on first use (per buffer set and options) and replayed afterwards;
- * calling qcams_set_instances invalidates it.  async.  Errors: EINVAL,
+ * (defaults: 1 workgroup per CU, refill_min 1, check_every 8, LPT, no
+ * graph).  With opts->graph the small set-up and analysis launches around
+ * the persistent kernel are captured into two HIP graphs on first use (per
+ * buffer set, order option and instance count) and replayed afterwards; the
+ * persistent kernel is launched between them.  async.  Errors: EINVAL,
  * ENOMEM, EHIP. */
 int qcams_run(qcams_ctx *ctx, const qcams_run_opts *opts, const qcams_state *st, double *sample,
               const qcams_outcome *out, int64_t *ids, double *xs, double *hist, void *stream);

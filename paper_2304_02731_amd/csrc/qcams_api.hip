@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <functional>
 #include <vector>
 
 #include "../../include/qcams.h"
@@ -39,8 +40,8 @@ struct qcams_ctx {
     int n_cu = 0;
     // captured launch sequence of qcams_run
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr, graph2_exec = nullptr;
+    hipGraph_t graph = nullptr, graph2 = nullptr;
     uint64_t graph_key[16] = {0};
     char err[512] = {0};
 };
@@ -612,6 +613,8 @@ void qcams_destroy(qcams_ctx* c)
     (void)hipSetDevice(c->device);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->graph2_exec) (void)hipGraphExecDestroy(c->graph2_exec);
+    if (c->graph2) (void)hipGraphDestroy(c->graph2);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->d_inst) (void)hipFree(c->d_inst);
     if (c->d_lpt_inst) (void)hipFree(c->d_lpt_inst);
@@ -821,33 +824,62 @@ int qcams_cross_sections(qcams_ctx* c, const qcams_outcome* out, const int64_t* 
 // ---------------------------------------------------------------------------
 // fused persistent run, launch-graph capture, autotuning
 // ---------------------------------------------------------------------------
-static int enqueue_run(qcams_ctx* c, const qcams_run_opts* o, const qcams_state* st,
-                       double* sample, const qcams_outcome* out, int64_t* ids, double* xs,
-                       double* hist, hipStream_t s)
+// The run is three launch groups: the small set-up kernels (work order,
+// initial conditions, counter reset), the persistent propagation kernel, and
+// the small analysis kernels (classification, reduction).  In graph mode the
+// two small groups are captured and replayed; the persistent kernel is one
+// launch either way and is bracketed by HIP events for its duration.
+static void enqueue_pre(qcams_ctx* c, const qcams_run_opts* o, const qcams_state* st,
+                        double* sample, int64_t* ids, hipStream_t s)
 {
     const int64_t n = c->n_total;
     const bool lpt = o->lpt != 0;
-    int64_t* order = c->d_order;
     hipLaunchKernelGGL(k_run_tables, dim3(grid_of(n, 256)), dim3(256), 0, s, c->d_inst, c->n_inst,
                        lpt ? c->d_lpt_inst : c->d_id_inst, lpt ? c->d_lpt_off : c->d_nat_off,
-                       c->d_nat_off, n, ids, order);
+                       c->d_nat_off, n, ids, c->d_order);
     dispatch_init(c, ids, n, st, sample, s);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, c->d_counter);
-    const int blocks = o->blocks > 0 ? o->blocks : 2 * c->n_cu;
+}
+
+static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const qcams_state* st,
+                              hipStream_t s)
+{
+    const int blocks = o->blocks > 0 ? o->blocks : c->n_cu;
     const int rm = o->refill_min < 1 ? 1 : (o->refill_min > 64 ? 64 : o->refill_min);
     const int ce = o->check_every < 1 ? 1 : o->check_every;
     if (hipEventRecord(c->ev_prop[0], s) != hipSuccess) return QCAMS_EHIP;
-    if (c->kinds == 0) launch_persistent<0, 0, 0>(c, blocks, rm, ce, order, st, s);
+    if (c->kinds == 0) launch_persistent<0, 0, 0>(c, blocks, rm, ce, c->d_order, st, s);
     else if (c->kinds == QCAMS_LJ + 3 * QCAMS_MORSE + 9 * QCAMS_BUCK)
-        launch_persistent<1, 0, 2>(c, blocks, rm, ce, order, st, s);
-    else launch_persistent<-1, -1, -1>(c, blocks, rm, ce, order, st, s);
+        launch_persistent<1, 0, 2>(c, blocks, rm, ce, c->d_order, st, s);
+    else launch_persistent<-1, -1, -1>(c, blocks, rm, ce, c->d_order, st, s);
     if (hipEventRecord(c->ev_prop[1], s) != hipSuccess) return QCAMS_EHIP;
+    return hipGetLastError() == hipSuccess ? QCAMS_OK : QCAMS_EHIP;
+}
+
+static void enqueue_post(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out,
+                         int64_t* ids, double* xs, double* hist, hipStream_t s)
+{
+    const int64_t n = c->n_total;
     hipLaunchKernelGGL(k_classify, dim3(grid_of(n, 128)), dim3(128), 0, s, c->sys, c->prm, st->d,
                        st->status, st->ld, n, out->label, out->vt, out->jt, out->d, out->ld);
     hipLaunchKernelGGL(k_xsec, dim3(c->n_inst), dim3(kRedThreads), 0, s, c->d_inst, c->n_inst,
                        c->sys.mu123, out->label, out->vt, out->d, out->ld, (const int64_t*)ids,
                        (const double*)nullptr, n, xs, hist);
-    return hipGetLastError() == hipSuccess ? QCAMS_OK : QCAMS_EHIP;
+}
+
+static int capture(qcams_ctx* c, hipGraph_t* g, hipGraphExec_t* x, const std::function<void(hipStream_t)>& f)
+{
+    if (*x) { HIP_OK(c, hipGraphExecDestroy(*x)); *x = nullptr; }
+    if (*g) { HIP_OK(c, hipGraphDestroy(*g)); *g = nullptr; }
+    if (!c->cap_stream) HIP_OK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_OK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    f(c->cap_stream);
+    hipGraph_t gg = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &gg);
+    if (e != hipSuccess) return fail(c, QCAMS_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    *g = gg;
+    HIP_OK(c, hipGraphInstantiate(x, gg, nullptr, nullptr, 0));
+    return QCAMS_OK;
 }
 
 int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, double* sample,
@@ -862,7 +894,7 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
     qcams_run_opts o{};
     o.blocks = 0;
     o.refill_min = 1;
-    o.check_every = 1;
+    o.check_every = 8;
     o.lpt = 1;
     o.graph = 0;
     if (opts) o = *opts;
@@ -895,41 +927,37 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
     }
     hipStream_t s = (hipStream_t)stream;
     if (!o.graph) {
-        if (enqueue_run(c, &o, st, sample, out, ids, xs, hist, s) != QCAMS_OK)
+        enqueue_pre(c, &o, st, sample, ids, s);
+        if (enqueue_persistent(c, &o, st, s) != QCAMS_OK)
             return fail(c, QCAMS_EHIP, "run launch: %s", hipGetErrorString(hipGetLastError()));
+        enqueue_post(c, st, out, ids, xs, hist, s);
+        HIP_OK(c, hipGetLastError());
         return QCAMS_OK;
     }
-    // graph: capture once per (buffers, options), replay afterwards
+    // graph mode: capture the two small launch groups once per (buffers,
+    // options, instance table), replay them around the persistent launch
     const uint64_t key[16] = {1,
                               (uint64_t)st->d, (uint64_t)st->nstep, (uint64_t)st->nrej,
                               (uint64_t)st->status, (uint64_t)st->ld, (uint64_t)sample,
                               (uint64_t)out->label, (uint64_t)out->d, (uint64_t)out->ld,
                               (uint64_t)ids, (uint64_t)xs, (uint64_t)hist,
-                              (uint64_t)o.blocks | ((uint64_t)o.refill_min << 32),
-                              (uint64_t)o.check_every | ((uint64_t)o.lpt << 32),
-                              ((uint64_t)out->vt ^ ((uint64_t)out->jt << 1)) + 1315423911ull *
-                                  ((uint64_t)c->n_total ^ ((uint64_t)c->n_inst << 40))};
+                              (uint64_t)o.lpt,
+                              (uint64_t)out->vt ^ ((uint64_t)out->jt << 1),
+                              (uint64_t)c->n_total ^ ((uint64_t)c->n_inst << 40)};
     if (memcmp(key, c->graph_key, sizeof key) != 0) {
-        if (c->graph_exec) {
-            HIP_OK(c, hipGraphExecDestroy(c->graph_exec));
-            c->graph_exec = nullptr;
-        }
-        if (c->graph) {
-            HIP_OK(c, hipGraphDestroy(c->graph));
-            c->graph = nullptr;
-        }
-        if (!c->cap_stream) HIP_OK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-        HIP_OK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        const int rc = enqueue_run(c, &o, st, sample, out, ids, xs, hist, c->cap_stream);
-        hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-        if (rc != QCAMS_OK || e != hipSuccess)
-            return fail(c, QCAMS_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-        c->graph = g;
-        HIP_OK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+        c->graph_key[0] = 0;
+        int rc = capture(c, &c->graph, &c->graph_exec,
+                         [&](hipStream_t cs) { enqueue_pre(c, &o, st, sample, ids, cs); });
+        if (rc == QCAMS_OK)
+            rc = capture(c, &c->graph2, &c->graph2_exec,
+                         [&](hipStream_t cs) { enqueue_post(c, st, out, ids, xs, hist, cs); });
+        if (rc != QCAMS_OK) return rc;
         memcpy(c->graph_key, key, sizeof key);
     }
     HIP_OK(c, hipGraphLaunch(c->graph_exec, s));
+    if (enqueue_persistent(c, &o, st, s) != QCAMS_OK)
+        return fail(c, QCAMS_EHIP, "run launch: %s", hipGetErrorString(hipGetLastError()));
+    HIP_OK(c, hipGraphLaunch(c->graph2_exec, s));
     return QCAMS_OK;
 }
 
