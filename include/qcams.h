@@ -56,8 +56,9 @@ extern "C" {
 #define QCAMS_BUCK 2  /* V = A exp(-b r) - C6 r^-6;  p = {A, b, C6} */
 
 /* ---- impact-parameter sampling ---- */
-#define QCAMS_B_FIXED 0 /* every trajectory at b */
-#define QCAMS_B_AREA 1  /* b = bmax sqrt(U): uniform over the disc of radius bmax */
+#define QCAMS_B_FIXED 0    /* every trajectory at b */
+#define QCAMS_B_AREA 1     /* b = bmax sqrt(U): uniform over the disc of radius bmax */
+#define QCAMS_B_PROPOSAL 2 /* (b^2, chi, cos theta) from the installed proposal, with weights */
 
 /* ---- trajectory status ---- */
 #define QCAMS_RUNNING 0
@@ -190,9 +191,10 @@ int qcams_set_instances(qcams_ctx *ctx, const qcams_instance *inst, int32_t n_in
 /* Initial conditions (Sec. 2.1, Eq. (5)-(6)) of trajectories ids[0..n)
  * (device int64, any order; each id must lie in an installed instance).
  * Writes st (all fields; h = 0, t = 0, status RUNNING, counters 0) and
- * sample [QCAMS_NS][st->ld] (device; may be NULL).  A trajectory whose id
- * is outside every instance, or whose b >= R, gets status FAIL_NONFINITE.
- * async. */
+ * sample [QCAMS_NS][st->ld] (device; may be NULL; its last row is the
+ * importance weight, 1 except for QCAMS_B_PROPOSAL instances).  A trajectory
+ * whose id is outside every instance, or whose b >= R, gets status
+ * FAIL_NONFINITE.  async. */
 int qcams_init_conditions(qcams_ctx *ctx, const int64_t *ids, int64_t n,
                           const qcams_state *st, double *sample, void *stream);
 
@@ -258,6 +260,90 @@ int qcams_last_run_kernel_ms(qcams_ctx *ctx, double *ms);
 
 int qcams_autotune(qcams_ctx *ctx, const qcams_state *st, const qcams_outcome *out, int64_t *ids,
                    double *xs, int32_t reps, qcams_run_opts *best, double *best_ms);
+
+/* ======================================================================
+ * Learned importance-sampling proposal.
+ *
+ * A network 6 -> 128 -> 128 -> 128 -> 4 (ReLU, softmax) estimates the
+ * probabilities of the outcome classes (quench, r1, r2, dissociation) of a
+ * trajectory from x = ((log10(E_c / K) - 3) / 2, b / 10 a0, v / 10, j / 10,
+ * chi, cos theta).  Its forward and backward passes run on BF16 matrix cores
+ * with FP32 accumulation; master weights, gradients and Adam state are FP32.
+ * Flat parameter layout (float): W1[6][128], b1[128], W2[128][128], b2,
+ * W3[128][128], b3, W4[128][4], b4 (W[i][o] input-major).
+ * ====================================================================== */
+#define QCAMS_MLP_NPARAM 34436
+#define QCAMS_MLP_NIN 6
+#define QCAMS_MLP_NOUT 4
+/* proposal cells: 32 (b^2) x 16 (chi) x 16 (cos theta), index (ib*16 + ichi)*16 + icos */
+#define QCAMS_PROP_CELLS 8192
+
+typedef struct qcams_mlp qcams_mlp;
+
+/* Create a network on `device`: params (host, [QCAMS_MLP_NPARAM]) or NULL
+ * for He-uniform weights (U(+-sqrt(6/fan_in)) from a hash of (seed, index))
+ * and zero biases.  Adam state zero.  sync.  Errors: ENOMEM, EHIP. */
+int qcams_mlp_create(qcams_mlp **mlp, int device, const float *params, uint64_t seed);
+
+/* Release the network.  NULL is allowed. */
+void qcams_mlp_destroy(qcams_mlp *mlp);
+
+/* Message of the last error on this network (or of the last failed create). */
+const char *qcams_mlp_last_error(const qcams_mlp *mlp);
+
+/* Copy the FP32 parameters to host memory [QCAMS_MLP_NPARAM].  sync. */
+int qcams_mlp_get_params(qcams_mlp *mlp, float *params);
+
+/* Replace the parameters (host [QCAMS_MLP_NPARAM]) and reset Adam.  sync. */
+int qcams_mlp_set_params(qcams_mlp *mlp, const float *params);
+
+/* Class probabilities prob (device [n][4] float) of inputs x (device [n][6]
+ * float).  async. */
+int qcams_mlp_forward(qcams_mlp *mlp, const float *x, int64_t n, float *prob, void *stream);
+
+/* Gradient (device [QCAMS_MLP_NPARAM] float) of the mean softmax
+ * cross-entropy over n rows: row r is x[idx[r]], y[idx[r]] (idx device int32
+ * [n], or NULL for r itself); labels y (device int32) in 0..3, a negative
+ * label contributes nothing (the mean still divides by n).  loss (device
+ * [1] float, may be NULL) receives the mean loss.  async. */
+int qcams_mlp_gradient(qcams_mlp *mlp, const float *x, const int32_t *y, const int32_t *idx,
+                       int64_t n, float *grad, float *loss, void *stream);
+
+/* One Adam step (Kingma & Ba 2015; beta 0.9 / 0.999, eps 1e-8) with the
+ * gradient grad (device [QCAMS_MLP_NPARAM]).  async. */
+int qcams_mlp_adam(qcams_mlp *mlp, const float *grad, float lr, void *stream);
+
+/* One epoch of minibatch training: batches of `batch` rows taken in the
+ * order perm (device int32 [n]; full batches only), each a gradient and an
+ * Adam step.  loss_sum (device [1] float) receives the sum of the batch
+ * losses.  The epoch's launches are captured once per argument set and
+ * replayed (update perm between epochs).  async. */
+int qcams_mlp_train_epoch(qcams_mlp *mlp, const float *x, const int32_t *y, const int32_t *perm,
+                          int64_t n, int32_t batch, float lr, float *loss_sum, void *stream);
+
+/* Network inputs and labels of classified trajectories: x (device [n][6]
+ * float) from each trajectory's instance (ids, device int64 [n]) and sample
+ * (device [QCAMS_NS][sample_ld]); y (device int32 [n]) = the label for
+ * quench / r1 / r2 / dissociation, -1 otherwise.  async. */
+int qcams_mlp_features(qcams_ctx *ctx, const int64_t *ids, const double *sample, int64_t sample_ld,
+                       const qcams_outcome *out, int64_t n, float *x, int32_t *y, void *stream);
+
+/* Build and install the proposal used by instances with b_mode
+ * QCAMS_B_PROPOSAL: for installed instance `inst` the network's probability
+ * pi_k of class `channel` at the centre of each cell k gives
+ * q_k = alpha / K + (1 - alpha) sqrt(pi_k) / sum_l sqrt(pi_l)  (K cells;
+ * alpha in (0, 1] keeps every weight <= 1/alpha).  A trajectory picks cell k
+ * with probability q_k and a uniform point inside it, and carries the weight
+ * (1/K) / q_k (1 exactly when alpha = 1).  q (device [QCAMS_PROP_CELLS]
+ * double, may be NULL) receives the table.  mlp may be NULL only with
+ * alpha = 1.  sync.  Errors: EINVAL, EHIP. */
+int qcams_proposal_build(qcams_ctx *ctx, qcams_mlp *mlp, int32_t inst, int32_t channel,
+                         double alpha, double *q);
+
+/* Install a given proposal table (host [QCAMS_PROP_CELLS], every entry > 0;
+ * normalised by the library) for QCAMS_B_PROPOSAL instances.  sync.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+int qcams_proposal_set(qcams_ctx *ctx, const double *q);
 
 #ifdef __cplusplus
 }

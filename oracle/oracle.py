@@ -104,6 +104,8 @@ def lib():
         L.orc_uniforms.argtypes = [C.c_uint64, C.c_int64, _dp]
         L.orc_init.argtypes = [C.POINTER(System), C.POINTER(Params), C.POINTER(Instance), _dp,
                                C.c_int64, _dp, _dp, _dp]
+        L.orc_init_q.argtypes = [C.POINTER(System), C.POINTER(Params), C.POINTER(Instance), _dp,
+                                 C.c_int64, _dp, _dp, _dp, _dp]
         L.orc_dopri5_tableau.argtypes = [_dp, _dp, _dp, _dp]
         L.orc_propagate.argtypes = [C.POINTER(System), C.POINTER(Params), _dp, _dp,
                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -114,9 +116,9 @@ def lib():
         L.orc_classify.argtypes = [C.POINTER(System), C.POINTER(Params), _dp] + \
             [C.POINTER(C.c_int)] * 3 + [_dp] * 5
         L.orc_run_one.argtypes = [C.POINTER(System), C.POINTER(Params), C.POINTER(Instance),
-                                  _dp, C.c_int64, C.POINTER(Record)]
+                                  _dp, C.c_int64, C.POINTER(Record), _dp]
         L.orc_run_batch.argtypes = [C.POINTER(System), C.POINTER(Params), C.POINTER(Instance),
-                                    _dp, C.POINTER(C.c_int64), C.c_int64, C.c_void_p]
+                                    _dp, C.POINTER(C.c_int64), C.c_int64, C.c_void_p, _dp]
         _lib = L
     return _lib
 
@@ -243,7 +245,7 @@ def philox4x64_10(ctr, key):
 
 
 def uniforms(seed: int, traj_id: int):
-    out, p = _arr(np.zeros(5))
+    out, p = _arr(np.zeros(6))
     lib().orc_uniforms(seed, traj_id, p)
     return out
 
@@ -269,12 +271,13 @@ def dopri5_tableau():
     return c, a.reshape(7, 7), b, bh
 
 
-def init(sys: System, prm: Params, inst: Instance, lev, traj_id: int):
+def init(sys: System, prm: Params, inst: Instance, lev, traj_id: int, prop_q=None):
     lv, pl = _arr(lev)
     y, py = _arr(np.zeros(12))
     aux, pa = _arr(np.zeros(6))
     smp, ps = _arr(np.zeros(6))
-    rc = lib().orc_init(C.byref(sys), C.byref(prm), C.byref(inst), pl, traj_id, py, pa, ps)
+    q, pq = _arr(prop_q) if prop_q is not None else (None, None)
+    rc = lib().orc_init_q(C.byref(sys), C.byref(prm), C.byref(inst), pl, traj_id, py, pa, ps, pq)
     if rc != 0:
         raise ValueError("oracle init failed: %d" % rc)
     return y, aux, smp
@@ -315,13 +318,14 @@ def classify(sys: System, prm: Params, y):
                 w=w.value, E=E, J2=J2)
 
 
-def run_batch(sys: System, prm: Params, inst: Instance, lev, ids) -> np.ndarray:
+def run_batch(sys: System, prm: Params, inst: Instance, lev, ids, prop_q=None) -> np.ndarray:
     ids = np.ascontiguousarray(ids, dtype=np.int64)
     out = np.zeros(len(ids), dtype=RECORD_DTYPE)
     lv, pl = _arr(lev)
+    q, pq = _arr(prop_q) if prop_q is not None else (None, None)
     rc = lib().orc_run_batch(C.byref(sys), C.byref(prm), C.byref(inst), pl,
                              ids.ctypes.data_as(C.POINTER(C.c_int64)), len(ids),
-                             out.ctypes.data_as(C.c_void_p))
+                             out.ctypes.data_as(C.c_void_p), pq)
     if rc != 0:
         raise ValueError("oracle run failed: %d" % rc)
     return out
@@ -338,14 +342,14 @@ def reduced_masses(sys: System):
 
 
 def _run_chunk(args):
-    wl_sys, wl_prm, inst, ids = args
+    wl_sys, wl_prm, inst, ids, prop_q = args
     sys = make_system(wl_sys)
     prm = make_params(wl_prm)
     lev = level(sys, inst.v, inst.j)
-    return run_batch(sys, prm, make_instance(inst), lev, ids)
+    return run_batch(sys, prm, make_instance(inst), lev, ids, prop_q)
 
 
-def run_workload(wl: W.Workload, ids_per_instance=None, processes: int = 1):
+def run_workload(wl: W.Workload, ids_per_instance=None, processes: int = 1, prop_q=None):
     """Run trajectories of a workload through the oracle.  ids_per_instance:
     optional list (one per instance) of global trajectory ids to run; default
     all.  Returns (records, instance index per record)."""
@@ -357,7 +361,7 @@ def run_workload(wl: W.Workload, ids_per_instance=None, processes: int = 1):
             continue
         step = max(1, (len(ids) + 4 * max(processes, 1) - 1) // (4 * max(processes, 1)))
         for s in range(0, len(ids), step):
-            jobs.append((k, (wl.system, wl.params, inst, ids[s:s + step])))
+            jobs.append((k, (wl.system, wl.params, inst, ids[s:s + step], prop_q)))
     if processes > 1:
         import multiprocessing as mp
         ctx = mp.get_context("fork")

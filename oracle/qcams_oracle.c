@@ -483,7 +483,8 @@ void orc_philox4x64_10(const uint64_t *ctr_in, const uint64_t *key_in, uint64_t 
 
 static double u01(uint64_t u) { return (double)(u >> 11) * (1.0 / 9007199254740992.0); }
 
-/* the five uniforms of one trajectory: b, cos(theta), phi, eta, chi */
+/* the six uniforms of one trajectory: b, cos(theta), phi, eta (block 0),
+ * chi and the proposal cell (block 1) */
 void orc_uniforms(uint64_t seed, int64_t id, double *u)
 {
     uint64_t key[2] = {seed, 0}, ctr[4] = {(uint64_t)id, 0, 0, 0}, out[4];
@@ -492,6 +493,31 @@ void orc_uniforms(uint64_t seed, int64_t id, double *u)
     ctr[1] = 1;
     orc_philox4x64_10(ctr, key, out);
     u[4] = u01(out[0]);
+    u[5] = u01(out[1]);
+}
+
+/* Importance-sampling proposal over cells of (b^2, chi, cos theta): 32 x 16
+ * x 16 cells of equal measure under the uniform sampling of Sec. 2.3, index
+ * (ib*16 + ichi)*16 + icos, cell probabilities q (any positive scale).  A
+ * draw picks the first cell whose running sum of q/sum(q) exceeds the cell
+ * uniform and a uniform point inside it; its weight is (1/K)/(q_k/sum q),
+ * which keeps the Monte Carlo estimates of Eq. (13) unbiased. */
+#define ORC_CELLS 8192
+static void proposal_draw(const double *q, const double *u, double bmax, double *b,
+                          double *cth, double *chi, double *w)
+{
+    double tot = 0.0, run = 0.0;
+    for (int i = 0; i < ORC_CELLS; ++i) tot += q[i];
+    int k = ORC_CELLS - 1;
+    for (int i = 0; i < ORC_CELLS; ++i) {
+        run += q[i];
+        if (run / tot > u[5]) { k = i; break; }
+    }
+    int ib = k / 256, ichi = (k / 16) % 16, ic = k % 16;
+    *b = bmax * sqrt((ib + u[0]) / 32.0);
+    *cth = -1.0 + (ic + u[1]) * (2.0 / 16.0);
+    *chi = (ichi + u[4]) / 16.0;
+    *w = (1.0 / ORC_CELLS) / (q[k] / tot);
 }
 
 /* ------------------------------------------------------------------ */
@@ -500,11 +526,12 @@ void orc_uniforms(uint64_t seed, int64_t id, double *u)
 /* aux = {t, tmax, rstop_eff, e0, escale, h}, sample = {b, cos(theta),   */
 /* phi, eta, chi, weight}.                                              */
 /* ------------------------------------------------------------------ */
-int orc_init(const orc_system *s, const orc_params *prm, const orc_instance *in,
-             const double *level, int64_t id, double *y, double *aux, double *sample)
+int orc_init_q(const orc_system *s, const orc_params *prm, const orc_instance *in,
+               const double *level, int64_t id, double *y, double *aux, double *sample,
+               const double *prop_q)
 {
     orc_masses k = masses_of(s);
-    double u[5];
+    double u[6];
     orc_uniforms(in->seed, id, u);
     /* READING: uniform measure d(Omega) = sin(theta) dtheta dphi deta dchi
      * (Sec. 2.3): cos(theta) in [-1,1), phi, eta in [0, 2pi), chi in [0,1).
@@ -514,6 +541,11 @@ int orc_init(const orc_system *s, const orc_params *prm, const orc_instance *in,
     double phi = 2.0 * M_PI * u[2];
     double eta = 2.0 * M_PI * u[3];
     double chi = u[4];
+    double wgt = 1.0;
+    if (in->b_mode == 2) {
+        if (!prop_q) return ORC_EINVAL;
+        proposal_draw(prop_q, u, in->bmax, &b, &cth, &chi, &wgt);
+    }
     double sth = sqrt(1.0 - cth * cth);
     double rp = level[2], tau = level[3];
     double jj = (double)in->j;
@@ -548,8 +580,14 @@ int orc_init(const orc_system *s, const orc_params *prm, const orc_instance *in,
     aux[4] = fmax(fabs(e0), fabs(level[0]));
     aux[5] = 0.0;
     sample[0] = b; sample[1] = cth; sample[2] = phi; sample[3] = eta; sample[4] = chi;
-    sample[5] = 1.0;
+    sample[5] = wgt;
     return ORC_OK;
+}
+
+int orc_init(const orc_system *s, const orc_params *prm, const orc_instance *in,
+             const double *level, int64_t id, double *y, double *aux, double *sample)
+{
+    return orc_init_q(s, prm, in, level, id, y, aux, sample, 0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -789,11 +827,11 @@ int orc_classify(const orc_system *s, const orc_params *prm, const double *y,
 /* One full trajectory and a batch driver.                              */
 /* ------------------------------------------------------------------ */
 int orc_run_one(const orc_system *s, const orc_params *prm, const orc_instance *in,
-                const double *level, int64_t id, orc_record *rec)
+                const double *level, int64_t id, orc_record *rec, const double *prop_q)
 {
     memset(rec, 0, sizeof *rec);
     double aux[6];
-    int rc = orc_init(s, prm, in, level, id, rec->y, aux, rec->sample);
+    int rc = orc_init_q(s, prm, in, level, id, rec->y, aux, rec->sample, prop_q);
     if (rc != ORC_OK) return rc;
     rec->status = orc_propagate(s, prm, rec->y, aux, &rec->nstep, &rec->nrej);
     rec->t = aux[0]; rec->tmax = aux[1]; rec->rstop = aux[2]; rec->e0 = aux[3];
@@ -810,10 +848,11 @@ int orc_run_one(const orc_system *s, const orc_params *prm, const orc_instance *
 
 /* Run trajectories ids[0..n) of instance `in` (level precomputed). */
 int orc_run_batch(const orc_system *s, const orc_params *prm, const orc_instance *in,
-                  const double *level, const int64_t *ids, int64_t n, orc_record *out)
+                  const double *level, const int64_t *ids, int64_t n, orc_record *out,
+                  const double *prop_q)
 {
     for (int64_t i = 0; i < n; ++i) {
-        int rc = orc_run_one(s, prm, in, level, ids[i], &out[i]);
+        int rc = orc_run_one(s, prm, in, level, ids[i], &out[i], prop_q);
         if (rc != ORC_OK) return rc;
     }
     return ORC_OK;

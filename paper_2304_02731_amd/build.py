@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqcams.so")
-SOURCES = [os.path.join(CSRC, "qcams_api.hip")]
+SOURCES = [os.path.join(CSRC, "qcams_api.hip"), os.path.join(CSRC, "qcams_mlp.hip")]
 HEADERS = [os.path.join(CSRC, "qcams_device.h"),
            os.path.join(os.path.dirname(HERE), "include", "qcams.h")]
 

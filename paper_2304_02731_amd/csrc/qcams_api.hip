@@ -37,6 +37,11 @@ struct qcams_ctx {
     int64_t* d_order = nullptr;                // [n_total] work item -> natural position
     int64_t order_cap = 0;
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
+    // importance-sampling proposal (cells of b^2, chi, cos theta)
+    double* d_prop_q = nullptr;
+    double* d_prop_cdf = nullptr;
+    float* d_cell_x = nullptr;   // network inputs at the cell centres
+    float* d_cell_p = nullptr;   // network outputs
     int n_cu = 0;
     // captured launch sequence of qcams_run
     hipStream_t cap_stream = nullptr;
@@ -107,20 +112,22 @@ __device__ inline int find_instance(const Inst* inst, int n_inst, int64_t id)
 template <int K0, int K1, int K2>
 __global__ void __launch_bounds__(256)
 k_init(Sys S, Prm P, const Inst* inst, int n_inst, const int64_t* ids, int64_t n, double* d,
-       int32_t* nstep, int32_t* nrej, uint8_t* status, int64_t ld, double* sample)
+       int32_t* nstep, int32_t* nrej, uint8_t* status, int64_t ld, double* sample,
+       const double* prop_q, const double* prop_cdf)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t id = ids[i];
     const int k = find_instance(inst, n_inst, id);
-    double x[6] = {0, 0, 0, 0, 0, 0}, p[6] = {0, 0, 0, 0, 0, 0}, smp[5] = {0, 0, 0, 0, 0};
+    double x[6] = {0, 0, 0, 0, 0, 0}, p[6] = {0, 0, 0, 0, 0, 0}, smp[6] = {0, 0, 0, 0, 0, 1};
     double tmax = 0.0, rstop = 0.0, e0 = 0.0, esc = 1.0, h = 0.0;
     uint8_t st = RUNNING;
     if (k < 0) {
         st = FAIL_NONFINITE;
     } else {
         const Inst I = inst[k];
-        if (!initial_state(S, P, I, id, x, p, tmax, rstop, smp)) st = FAIL_NONFINITE;
+        if (I.b_mode == 2 && !prop_q) st = FAIL_NONFINITE;
+        else if (!initial_state(S, P, I, id, x, p, tmax, rstop, smp, prop_q, prop_cdf)) st = FAIL_NONFINITE;
         e0 = hamiltonian(S, x, p);
         esc = fmax(fabs(e0), fabs(I.Evj));
         // starting step of the RK5(4) controller (fixed step: h_fixed)
@@ -144,10 +151,8 @@ k_init(Sys S, Prm P, const Inst* inst, int n_inst, const int64_t* ids, int64_t n
     nstep[i] = 0;
     nrej[i] = 0;
     status[i] = st;
-    if (sample) {
-        for (int f = 0; f < 5; ++f) sample[f * ld + i] = smp[f];
-        sample[5 * ld + i] = 1.0;
-    }
+    if (sample)
+        for (int f = 0; f < 6; ++f) sample[f * ld + i] = smp[f];
 }
 
 // ---------------------------------------------------------------------------
@@ -437,7 +442,7 @@ k_xsec(const Inst* inst, int n_inst, double mu123, const uint8_t* label, const i
     const double N = (double)(e - b);
     row[0] = N;
     for (int c = 0; c < 6; ++c) row[1 + c] = acc[c];
-    const double area = I.b_mode == QCAMS_B_AREA ? kPi * I.bmax * I.bmax : NAN;
+    const double area = I.b_mode != QCAMS_B_FIXED ? kPi * I.bmax * I.bmax : NAN;
     const double speed = sqrt(2.0 * I.Ec / mu123);
     for (int c = 0; c < 4; ++c) {
         const double m = N > 0 ? acc[6 + c] / N : NAN;
@@ -455,6 +460,107 @@ k_xsec(const Inst* inst, int n_inst, double mu123, const uint8_t* label, const i
     row[29] = acc[15];
     row[30] = 0.0;
     row[31] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// learned proposal: network inputs, cell table, cumulative distribution
+// ---------------------------------------------------------------------------
+constexpr double kFeatB = 10.0;   // impact parameter scale of the input (a0)
+
+__device__ inline void features(double Ec_hartree, double b, int v, int j, double chi, double cth,
+                                float* x)
+{
+    const double EK = Ec_hartree / 3.1668115634556e-6;
+    x[0] = (float)((log10(EK) - 3.0) * 0.5);
+    x[1] = (float)(b / kFeatB);
+    x[2] = (float)(v * 0.1);
+    x[3] = (float)(j * 0.1);
+    x[4] = (float)chi;
+    x[5] = (float)cth;
+}
+
+__global__ void k_mlp_features(const Inst* inst, int n_inst, const int64_t* ids, const double* sample,
+                               int64_t sld, const uint8_t* label, int64_t n, float* x, int32_t* y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = find_instance(inst, n_inst, ids[i]);
+    float f[6] = {0, 0, 0, 0, 0, 0};
+    int lab = -1;
+    if (k >= 0) {
+        const Inst I = inst[k];
+        features(I.Ec, sample[0 * sld + i], I.v, I.j, sample[4 * sld + i], sample[1 * sld + i], f);
+        lab = label[i] < 4 ? (int)label[i] : -1;
+    }
+    for (int c = 0; c < 6; ++c) x[i * 6 + c] = f[c];
+    y[i] = lab;
+}
+
+__global__ void k_cell_features(const Inst* inst, int k, float* x)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= kCells) return;
+    const Inst I = inst[k];
+    const int ib = c / (kCellsChi * kCellsCos), ichi = (c / kCellsCos) % kCellsChi, ic = c % kCellsCos;
+    const double b = I.bmax * sqrt((ib + 0.5) / kCellsB);
+    const double chi = (ichi + 0.5) / kCellsChi;
+    const double cth = -1.0 + (ic + 0.5) * (2.0 / kCellsCos);
+    features(I.Ec, b, I.v, I.j, chi, cth, x + 6 * c);
+}
+
+// q_k = alpha / K + (1 - alpha) sqrt(pi_k) / sum sqrt(pi); one block, fixed
+// summation order.  With prob == NULL, q_k = 1/K.
+__global__ void __launch_bounds__(256) k_prop_q(const float* prob, int channel, double alpha, double* q)
+{
+    __shared__ double part[256];
+    const int t = threadIdx.x;
+    constexpr int per = kCells / 256;
+    double s = 0.0;
+    for (int e = 0; e < per; ++e) {
+        const int c = t * per + e;
+        s += prob ? sqrt(fmax((double)prob[4 * c + channel], 0.0)) : 0.0;
+    }
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int u = 0; u < 256; ++u) tot += part[u];
+        part[0] = tot;
+    }
+    __syncthreads();
+    const double tot = part[0];
+    for (int e = 0; e < per; ++e) {
+        const int c = t * per + e;
+        const double r = (prob && tot > 0.0) ? sqrt(fmax((double)prob[4 * c + channel], 0.0)) / tot : 0.0;
+        q[c] = (prob && tot > 0.0 && alpha < 1.0) ? alpha / kCells + (1.0 - alpha) * r : 1.0 / kCells;
+    }
+}
+
+// normalised cumulative distribution of q (fixed order: 256 chunks of 32)
+__global__ void __launch_bounds__(256) k_prop_cdf(double* q, double* cdf)
+{
+    __shared__ double part[257];
+    const int t = threadIdx.x;
+    constexpr int per = kCells / 256;
+    double s = 0.0;
+    for (int e = 0; e < per; ++e) s += q[t * per + e];
+    part[t + 1] = s;
+    __syncthreads();
+    if (t == 0) {
+        part[0] = 0.0;
+        for (int u = 1; u <= 256; ++u) part[u] += part[u - 1];
+    }
+    __syncthreads();
+    const double tot = part[256];
+    double run = part[t];
+    for (int e = 0; e < per; ++e) {
+        const int c = t * per + e;
+        run += q[c];
+        cdf[c] = run / tot;
+    }
+    __syncthreads();
+    for (int e = 0; e < per; ++e) q[t * per + e] /= tot;
+    if (t == 255) cdf[kCells - 1] = 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -495,7 +601,7 @@ static void launch_init(qcams_ctx* c, const int64_t* ids, int64_t n, const qcams
 {
     hipLaunchKernelGGL((k_init<K0, K1, K2>), dim3(grid_of(n, 256)), dim3(256), 0, s, c->sys, c->prm,
                        c->d_inst, c->n_inst, ids, n, st->d, st->nstep, st->nrej, st->status,
-                       st->ld, sample);
+                       st->ld, sample, (const double*)c->d_prop_q, (const double*)c->d_prop_cdf);
 }
 
 static void dispatch_init(qcams_ctx* c, const int64_t* ids, int64_t n, const qcams_state* st,
@@ -625,6 +731,8 @@ void qcams_destroy(qcams_ctx* c)
     if (c->d_order) (void)hipFree(c->d_order);
     for (int e = 0; e < 2; ++e)
         if (c->ev_prop[e]) (void)hipEventDestroy(c->ev_prop[e]);
+    for (void* q : {(void*)c->d_prop_q, (void*)c->d_prop_cdf, (void*)c->d_cell_x, (void*)c->d_cell_p})
+        if (q) (void)hipFree(q);
     delete c;
 }
 
@@ -675,9 +783,9 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
     for (int k = 0; k < n_inst; ++k) {
         const qcams_instance& q = inst[k];
         if (!(q.Ec_K > 0.0) || q.n_traj < 0 || q.first_id < 0 ||
-            (q.b_mode != QCAMS_B_FIXED && q.b_mode != QCAMS_B_AREA) ||
+            (q.b_mode != QCAMS_B_FIXED && q.b_mode != QCAMS_B_AREA && q.b_mode != QCAMS_B_PROPOSAL) ||
             (q.b_mode == QCAMS_B_FIXED && !(q.b >= 0.0)) ||
-            (q.b_mode == QCAMS_B_AREA && !(q.bmax >= 0.0)))
+            (q.b_mode != QCAMS_B_FIXED && !(q.bmax >= 0.0)))
             return fail(c, QCAMS_EINVAL, "instance %d: invalid fields", k);
         if (k > 0 && q.first_id < inst[k - 1].first_id + inst[k - 1].n_traj)
             return fail(c, QCAMS_EINVAL, "instance %d: ids overlap or are not sorted", k);
@@ -702,7 +810,7 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
         h[k].rminus = lev[4 * k + 1];
         h[k].rplus = lev[4 * k + 2];
         h[k].tau = lev[4 * k + 3];
-        const double b = inst[k].b_mode == QCAMS_B_AREA ? inst[k].bmax : inst[k].b;
+        const double b = inst[k].b_mode == QCAMS_B_FIXED ? inst[k].b : inst[k].bmax;
         if (!(b < c->prm.R0)) return fail(c, QCAMS_EINVAL, "instance %d: impact parameter >= R0", k);
     }
     HIP_OK(c, hipSetDevice(c->device));
@@ -857,14 +965,15 @@ static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const qcams
 }
 
 static void enqueue_post(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out,
-                         int64_t* ids, double* xs, double* hist, hipStream_t s)
+                         int64_t* ids, double* sample, double* xs, double* hist, hipStream_t s)
 {
     const int64_t n = c->n_total;
     hipLaunchKernelGGL(k_classify, dim3(grid_of(n, 128)), dim3(128), 0, s, c->sys, c->prm, st->d,
                        st->status, st->ld, n, out->label, out->vt, out->jt, out->d, out->ld);
     hipLaunchKernelGGL(k_xsec, dim3(c->n_inst), dim3(kRedThreads), 0, s, c->d_inst, c->n_inst,
                        c->sys.mu123, out->label, out->vt, out->d, out->ld, (const int64_t*)ids,
-                       (const double*)nullptr, n, xs, hist);
+                       sample ? (const double*)(sample + 5 * st->ld) : (const double*)nullptr, n,
+                       xs, hist);
 }
 
 static int capture(qcams_ctx* c, hipGraph_t* g, hipGraphExec_t* x, const std::function<void(hipStream_t)>& f)
@@ -900,6 +1009,9 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
     if (opts) o = *opts;
     if (o.blocks < 0 || o.refill_min < 0 || o.check_every < 0)
         return fail(c, QCAMS_EINVAL, "negative run option");
+    for (const Inst& I : c->h_inst)
+        if (I.b_mode == 2 && (!sample || !c->d_prop_q))
+            return fail(c, QCAMS_EINVAL, "proposal instances need a sample buffer and a proposal");
     HIP_OK(c, hipSetDevice(c->device));
     if (!c->d_counter) {
         if (hipMalloc(&c->d_counter, sizeof(unsigned long long)) != hipSuccess) {
@@ -930,7 +1042,7 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
         enqueue_pre(c, &o, st, sample, ids, s);
         if (enqueue_persistent(c, &o, st, s) != QCAMS_OK)
             return fail(c, QCAMS_EHIP, "run launch: %s", hipGetErrorString(hipGetLastError()));
-        enqueue_post(c, st, out, ids, xs, hist, s);
+        enqueue_post(c, st, out, ids, sample, xs, hist, s);
         HIP_OK(c, hipGetLastError());
         return QCAMS_OK;
     }
@@ -950,7 +1062,7 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
                          [&](hipStream_t cs) { enqueue_pre(c, &o, st, sample, ids, cs); });
         if (rc == QCAMS_OK)
             rc = capture(c, &c->graph2, &c->graph2_exec,
-                         [&](hipStream_t cs) { enqueue_post(c, st, out, ids, xs, hist, cs); });
+                         [&](hipStream_t cs) { enqueue_post(c, st, out, ids, sample, xs, hist, cs); });
         if (rc != QCAMS_OK) return rc;
         memcpy(c->graph_key, key, sizeof key);
     }
@@ -1027,6 +1139,77 @@ int qcams_last_run_kernel_ms(qcams_ctx* c, double* ms)
     float f = 0.f;
     HIP_OK(c, hipEventElapsedTime(&f, c->ev_prop[0], c->ev_prop[1]));
     *ms = (double)f;
+    return QCAMS_OK;
+}
+
+
+int qcams_mlp_features(qcams_ctx* c, const int64_t* ids, const double* sample, int64_t sample_ld,
+                       const qcams_outcome* out, int64_t n, float* x, int32_t* y, void* stream)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    if (c->n_inst < 1) return fail(c, QCAMS_EINVAL, "no instances installed");
+    if (n < 0 || (n > 0 && (!ids || !sample || !out || !out->label || !x || !y || sample_ld < n)))
+        return fail(c, QCAMS_EINVAL, "bad arguments");
+    if (n == 0) return QCAMS_OK;
+    HIP_OK(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_mlp_features, dim3(grid_of(n, 256)), dim3(256), 0, (hipStream_t)stream,
+                       c->d_inst, c->n_inst, ids, sample, sample_ld, out->label, n, x, y);
+    HIP_OK(c, hipGetLastError());
+    return QCAMS_OK;
+}
+
+static int ensure_prop(qcams_ctx* c)
+{
+    if (c->d_prop_q) return QCAMS_OK;
+    if (hipMalloc(&c->d_prop_q, kCells * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_prop_cdf, kCells * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_cell_x, kCells * 6 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->d_cell_p, kCells * 4 * sizeof(float)) != hipSuccess)
+        return fail(c, QCAMS_ENOMEM, "proposal tables allocation failed");
+    return QCAMS_OK;
+}
+
+int qcams_proposal_build(qcams_ctx* c, qcams_mlp* mlp, int32_t inst, int32_t channel, double alpha,
+                         double* q)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    if (inst < 0 || inst >= c->n_inst || channel < 0 || channel > 3 || !(alpha > 0.0) || !(alpha <= 1.0) ||
+        (!mlp && alpha < 1.0))
+        return fail(c, QCAMS_EINVAL, "bad arguments");
+    HIP_OK(c, hipSetDevice(c->device));
+    if (int rc = ensure_prop(c)) return rc;
+    const float* prob = nullptr;
+    if (mlp && alpha < 1.0) {
+        hipLaunchKernelGGL(k_cell_features, dim3(kCells / 256), dim3(256), 0, 0, c->d_inst, inst, c->d_cell_x);
+        HIP_OK(c, hipGetLastError());
+        const int rc = qcams_mlp_forward(mlp, c->d_cell_x, kCells, c->d_cell_p, nullptr);
+        if (rc != QCAMS_OK) return fail(c, rc, "network forward: %s", qcams_mlp_last_error(mlp));
+        prob = c->d_cell_p;
+    }
+    hipLaunchKernelGGL(k_prop_q, dim3(1), dim3(256), 0, 0, prob, channel, alpha, c->d_prop_q);
+    hipLaunchKernelGGL(k_prop_cdf, dim3(1), dim3(256), 0, 0, c->d_prop_q, c->d_prop_cdf);
+    HIP_OK(c, hipGetLastError());
+    if (q) HIP_OK(c, hipMemcpy(q, c->d_prop_q, kCells * sizeof(double), hipMemcpyDeviceToDevice));
+    HIP_OK(c, hipDeviceSynchronize());
+    return QCAMS_OK;
+}
+
+int qcams_proposal_set(qcams_ctx* c, const double* q_host)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    if (!q_host) return fail(c, QCAMS_EINVAL, "null table");
+    double tot = 0.0;
+    for (int k = 0; k < kCells; ++k) {
+        if (!(q_host[k] > 0.0) || !is_finite(q_host[k]))
+            return fail(c, QCAMS_EINVAL, "cell %d: probability must be positive and finite", k);
+        tot += q_host[k];
+    }
+    HIP_OK(c, hipSetDevice(c->device));
+    if (int rc = ensure_prop(c)) return rc;
+    HIP_OK(c, hipMemcpy(c->d_prop_q, q_host, kCells * sizeof(double), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_prop_cdf, dim3(1), dim3(256), 0, 0, c->d_prop_q, c->d_prop_cdf);
+    HIP_OK(c, hipGetLastError());
+    HIP_OK(c, hipDeviceSynchronize());
     return QCAMS_OK;
 }
 

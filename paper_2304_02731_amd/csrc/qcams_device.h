@@ -529,9 +529,10 @@ QD void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1)
 
 QD double to_unit(uint64_t u) { return (double)(u >> 11) * 0x1.0p-53; }
 
-// Five uniforms of trajectory `id`: words 0-3 of block 0 and word 0 of
-// block 1 of the stream keyed by (seed, 0), counter (id, block, 0, 0).
-QD void uniforms5(uint64_t seed, int64_t id, double* u)
+// Six uniforms of trajectory `id`: words 0-3 of block 0 (b, cos theta, phi,
+// eta) and words 0-1 of block 1 (chi, proposal cell) of the stream keyed by
+// (seed, 0), counter (id, block, 0, 0).
+QD void uniforms6(uint64_t seed, int64_t id, double* u)
 {
     uint64_t c[4] = {(uint64_t)id, 0, 0, 0};
     philox4x64(c, seed, 0);
@@ -542,6 +543,22 @@ QD void uniforms5(uint64_t seed, int64_t id, double* u)
     uint64_t d[4] = {(uint64_t)id, 1, 0, 0};
     philox4x64(d, seed, 0);
     u[4] = to_unit(d[0]);
+    u[5] = to_unit(d[1]);
+}
+
+// proposal cells: 32 (b^2) x 16 (chi) x 16 (cos theta)
+constexpr int kCellsB = 32, kCellsChi = 16, kCellsCos = 16;
+constexpr int kCells = kCellsB * kCellsChi * kCellsCos;
+
+// first cell whose cumulative probability exceeds u
+QD int find_cell(const double* cdf, double u)
+{
+    int lo = 0, hi = kCells - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] > u) hi = mid; else lo = mid + 1;
+    }
+    return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -552,15 +569,29 @@ QD void uniforms5(uint64_t seed, int64_t id, double* u)
 // t_max = t_stop R / v_c; r_stop_eff = r_stop + (R - R0).
 // ---------------------------------------------------------------------------
 QD bool initial_state(const Sys& S, const Prm& P, const Inst& I, int64_t id, double* x,
-                      double* p, double& tmax, double& rstop, double* smp)
+                      double* p, double& tmax, double& rstop, double* smp, const double* prop_q,
+                      const double* prop_cdf)
 {
-    double u[5];
-    uniforms5(I.seed, id, u);
-    const double b = I.b_mode == 1 ? I.bmax * sqrt(u[0]) : I.b;
-    const double cth = 2.0 * u[1] - 1.0;
+    double u[6];
+    uniforms6(I.seed, id, u);
+    double b = I.b_mode == 1 ? I.bmax * sqrt(u[0]) : I.b;
+    double cth = 2.0 * u[1] - 1.0;
     const double phi = 2.0 * kPi * u[2];
     const double eta = 2.0 * kPi * u[3];
-    const double chi = u[4];
+    double chi = u[4];
+    double w = 1.0;
+    if (I.b_mode == 2) {
+        // importance sampling: cell k with probability q_k, uniform inside
+        // it; weight = (uniform cell probability) / q_k
+        const int k = find_cell(prop_cdf, u[5]);
+        const int ib = k / (kCellsChi * kCellsCos);
+        const int ichi = (k / kCellsCos) % kCellsChi;
+        const int ic = k % kCellsCos;
+        b = I.bmax * sqrt((ib + u[0]) * (1.0 / kCellsB));
+        cth = -1.0 + (ic + u[1]) * (2.0 / kCellsCos);
+        chi = (ichi + u[4]) * (1.0 / kCellsChi);
+        w = (1.0 / kCells) / prop_q[k];
+    }
     const double sth = sqrt(1.0 - cth * cth);
     double sph, cph, set, cet;
     sincos(phi, &sph, &cph);
@@ -592,6 +623,7 @@ QD bool initial_state(const Sys& S, const Prm& P, const Inst& I, int64_t id, dou
     smp[2] = phi;
     smp[3] = eta;
     smp[4] = chi;
+    smp[5] = w;
     return b < R;
 }
 

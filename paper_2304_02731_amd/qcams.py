@@ -23,7 +23,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "qcams.h")
 # ---- constants mirrored from include/qcams.h ----
 OK, EINVAL, EUNBOUND, ENOROOT, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
 MORSE, LJ, BUCK = 0, 1, 2
-B_FIXED, B_AREA = 0, 1
+B_FIXED, B_AREA, B_PROPOSAL = 0, 1, 2
+MLP_NPARAM, MLP_NIN, MLP_NOUT, PROP_CELLS = 34436, 6, 4, 8192
 RUNNING, OK_RSTOP, OK_TMAX, FAIL_MAXSTEPS, FAIL_NONFINITE, FAIL_HMIN, COLLAPSE = range(7)
 QUENCH, R1, R2, DISS, UNRESOLVED, FAILED = range(6)
 NF, NS, XS_STRIDE, VMAX = 18, 6, 32, 64
@@ -117,6 +118,20 @@ def lib():
     L.qcams_last_run_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
     L.qcams_autotune.argtypes = [vp, C.POINTER(StateC), C.POINTER(OutcomeC), vp, vp, i32,
                                  C.POINTER(RunOpts), C.POINTER(C.c_double)]
+    L.qcams_mlp_create.argtypes = [C.POINTER(vp), C.c_int, vp, C.c_uint64]
+    L.qcams_mlp_destroy.argtypes = [vp]
+    L.qcams_mlp_destroy.restype = None
+    L.qcams_mlp_last_error.argtypes = [vp]
+    L.qcams_mlp_last_error.restype = C.c_char_p
+    L.qcams_mlp_get_params.argtypes = [vp, vp]
+    L.qcams_mlp_set_params.argtypes = [vp, vp]
+    L.qcams_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.qcams_mlp_gradient.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+    L.qcams_mlp_adam.argtypes = [vp, vp, C.c_float, vp]
+    L.qcams_mlp_train_epoch.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, vp, vp]
+    L.qcams_mlp_features.argtypes = [vp, vp, vp, i64, C.POINTER(OutcomeC), i64, vp, vp, vp]
+    L.qcams_proposal_build.argtypes = [vp, vp, i32, i32, C.c_double, vp]
+    L.qcams_proposal_set.argtypes = [vp, vp]
     for name in exported_names():
         getattr(L, name)  # raises if a declared symbol is missing
     _lib = L
@@ -358,8 +373,107 @@ class Context:
                     "qcams_autotune")
         return best, ms.value
 
+    # ---- learned proposal ----
+    def mlp_features(self, ids, sample, outcome: Outcome, n: Optional[int] = None, stream=None):
+        """Network inputs x [n, 6] (float32) and labels y [n] (int32, -1 = not a
+        class) of classified trajectories."""
+        import torch
+        n = ids.numel() if n is None else n
+        x = torch.zeros((n, MLP_NIN), dtype=torch.float32, device=self.torch_device)
+        y = torch.zeros(n, dtype=torch.int32, device=self.torch_device)
+        self._check(lib().qcams_mlp_features(self._h, ids.data_ptr(), sample.data_ptr(),
+                                             sample.shape[1], C.byref(outcome.c()), n,
+                                             x.data_ptr(), y.data_ptr(), _stream(stream)),
+                    "qcams_mlp_features")
+        return x, y
+
+    def proposal_build(self, mlp, inst: int, channel: int, alpha: float):
+        """Build and install the proposal of instance `inst` for `channel`;
+        returns the cell probabilities q [PROP_CELLS] (float64, device)."""
+        import torch
+        q = torch.zeros(PROP_CELLS, dtype=torch.float64, device=self.torch_device)
+        self._check(lib().qcams_proposal_build(self._h, mlp._h if mlp is not None else None, inst,
+                                               channel, alpha, q.data_ptr()), "qcams_proposal_build")
+        return q
+
+    def proposal_set(self, q):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        assert q.shape == (PROP_CELLS,)
+        self._check(lib().qcams_proposal_set(self._h, q.ctypes.data), "qcams_proposal_set")
+
     def all_ids(self):
         import torch
         ids = [torch.arange(i.first_id, i.first_id + i.n_traj, dtype=torch.int64)
                for i in self.instances]
         return torch.cat(ids).to(self.torch_device)
+
+
+class MLP:
+    """The proposal network (qcams_mlp): 6 -> 128 -> 128 -> 128 -> 4."""
+
+    def __init__(self, params=None, seed: int = 0, device: int = 0):
+        import torch
+        self.torch_device = torch.device("cuda", device)
+        L = lib()
+        h = C.c_void_p()
+        p = None
+        if params is not None:
+            self._init = np.ascontiguousarray(params, dtype=np.float32)
+            assert self._init.shape == (MLP_NPARAM,)
+            p = self._init.ctypes.data
+        with torch.cuda.device(device):
+            rc = L.qcams_mlp_create(C.byref(h), device, p, seed)
+        if rc != OK:
+            raise QcamsError("qcams_mlp_create failed (%d): %s" % (rc, L.qcams_mlp_last_error(None).decode()))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qcams_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise QcamsError("%s failed (%d): %s" % (what, rc, lib().qcams_mlp_last_error(self._h).decode()))
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(lib().qcams_mlp_get_params(self._h, out.ctypes.data), "qcams_mlp_get_params")
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(lib().qcams_mlp_set_params(self._h, p.ctypes.data), "qcams_mlp_set_params")
+
+    def forward(self, x, stream=None):
+        import torch
+        n = x.shape[0]
+        prob = torch.zeros((n, MLP_NOUT), dtype=torch.float32, device=self.torch_device)
+        self._check(lib().qcams_mlp_forward(self._h, x.data_ptr(), n, prob.data_ptr(), _stream(stream)),
+                    "qcams_mlp_forward")
+        return prob
+
+    def gradient(self, x, y, idx=None, n: Optional[int] = None, stream=None):
+        import torch
+        n = (idx.numel() if idx is not None else x.shape[0]) if n is None else n
+        g = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=self.torch_device)
+        loss = torch.zeros(1, dtype=torch.float32, device=self.torch_device)
+        self._check(lib().qcams_mlp_gradient(self._h, x.data_ptr(), y.data_ptr(),
+                                             idx.data_ptr() if idx is not None else None, n,
+                                             g.data_ptr(), loss.data_ptr(), _stream(stream)),
+                    "qcams_mlp_gradient")
+        return g, loss
+
+    def adam(self, grad, lr: float, stream=None):
+        self._check(lib().qcams_mlp_adam(self._h, grad.data_ptr(), lr, _stream(stream)), "qcams_mlp_adam")
+
+    def train_epoch(self, x, y, perm, batch: int, lr: float, loss_sum, stream=None):
+        self._check(lib().qcams_mlp_train_epoch(self._h, x.data_ptr(), y.data_ptr(), perm.data_ptr(),
+                                                perm.numel(), batch, lr, loss_sum.data_ptr(),
+                                                _stream(stream)), "qcams_mlp_train_epoch")

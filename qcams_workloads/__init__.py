@@ -32,7 +32,7 @@ LABEL_NAMES = ("quench", "r1_AC+B", "r2_BC+A", "diss", "unresolved", "failed")
 RUNNING, OK_RSTOP, OK_TMAX, FAIL_MAXSTEPS, FAIL_NONFINITE, FAIL_HMIN, COLLAPSE = range(7)
 
 # impact-parameter modes
-B_FIXED, B_AREA = 0, 1
+B_FIXED, B_AREA, B_PROPOSAL = 0, 1, 2
 
 
 @dataclasses.dataclass(frozen=True)

@@ -35,14 +35,14 @@ def test_uniform_stream(orc):
     seed = 230402731
     u = np.array([orc.uniforms(seed, i) for i in range(4000)])
     assert u.min() >= 0.0 and u.max() < 1.0
-    for c in range(5):
+    for c in range(6):
         assert stats.kstest(u[:, c], "uniform").pvalue > 1e-3
-    # the five draws of one trajectory are the first four words of block 0
-    # and the first word of block 1
+    # the six draws of one trajectory are the four words of block 0 and the
+    # first two words of block 1
     raw0 = orc.philox4x64_10((7, 0, 0, 0), (seed, 0))
     raw1 = orc.philox4x64_10((7, 1, 0, 0), (seed, 0))
     u7 = orc.uniforms(seed, 7)
-    expect = [(x >> 11) * 2.0 ** -53 for x in raw0] + [(raw1[0] >> 11) * 2.0 ** -53]
+    expect = [(x >> 11) * 2.0 ** -53 for x in raw0] + [(x >> 11) * 2.0 ** -53 for x in raw1[:2]]
     assert list(u7) == expect
 
 
@@ -134,3 +134,36 @@ def test_initial_state_classifies_as_its_level(orc):
             assert c["jt"] == j and c["vt"] == v
             assert c["jprime"] == pytest.approx(j, abs=1e-12)
             assert c["vprime"] == pytest.approx(v, abs=1e-9)
+
+
+def test_proposal_draws(orc):
+    """Importance sampling over (b^2, chi, cos theta) cells: with a uniform
+    table every weight is exactly 1 and the cells are uniform; with a skewed
+    table the weights average to 1 (unbiasedness) and the cell frequencies
+    follow the table."""
+    K = 8192
+    wl, sys, prm, inst, lev = _setup(orc, 0, 0)
+    inst.b_mode = W.B_PROPOSAL
+    q = np.ones(K)
+    S = np.array([orc.init(sys, prm, inst, lev, t, prop_q=q)[2] for t in range(2000)])
+    assert np.all(S[:, 5] == 1.0)
+    assert stats.kstest((S[:, 0] / 10.0) ** 2, "uniform").pvalue > 1e-3
+    assert stats.kstest((S[:, 1] + 1) / 2, "uniform").pvalue > 1e-3
+    assert stats.kstest(S[:, 4], "uniform").pvalue > 1e-3
+    rng = np.random.default_rng(3)
+    q = rng.uniform(0.05, 1.0, K)
+    q[:256] *= 20.0                     # favour the smallest impact parameters
+    S = np.array([orc.init(sys, prm, inst, lev, t, prop_q=q)[2] for t in range(6000)])
+    w = S[:, 5]
+    assert abs(w.mean() - 1.0) < 4 * w.std() / np.sqrt(len(w))
+    frac_small_b = ((S[:, 0] / 10.0) ** 2 < 1.0 / 32).mean()
+    expect = q[:256].sum() / q.sum()
+    assert abs(frac_small_b - expect) < 4 * np.sqrt(expect * (1 - expect) / len(w))
+    # the weight is (1/K) / (q_k / sum q) of the drawn cell
+    for t in range(20):
+        smp = S[t]
+        ib = min(int((smp[0] / 10.0) ** 2 * 32), 31)
+        ichi = min(int(smp[4] * 16), 15)
+        ic = min(int((smp[1] + 1) * 8), 15)
+        k = (ib * 16 + ichi) * 16 + ic
+        assert smp[5] == pytest.approx((1.0 / K) / (q[k] / q.sum()), rel=1e-12)
