@@ -141,8 +141,8 @@ __device__ inline void load_x16(const float* x, const int32_t* idx, int64_t row0
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_mlp_forward(Weights W, const float* x, int64_t n, float* prob)
 {
-    __shared__ __bf16 s_x[4][16 * kInP];
-    __shared__ __bf16 s_h[3][4][16 * kHid];
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[4][16 * kInP];
+    __shared__ __attribute__((aligned(16))) __bf16 s_h[3][4][16 * kHid];
     __shared__ float s_lg[4][16 * kOut];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t row0 = (int64_t)blockIdx.x * kTile + 16 * wave;
@@ -165,9 +165,9 @@ __global__ void __launch_bounds__(256)
 k_mlp_grad(Weights W, const float* x, const int32_t* y, const int32_t* idx, int64_t n,
            float inv_n, float* partial, float* loss_part)
 {
-    __shared__ __bf16 s_x[kTile * kInP];              // H0
-    __shared__ __bf16 s_h[3][kTile * kHid];           // H1..H3
-    __shared__ __bf16 s_dz[kTile * kHid];             // bf16 dZ of the current layer
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[kTile * kInP];              // H0
+    __shared__ __attribute__((aligned(16))) __bf16 s_h[3][kTile * kHid];           // H1..H3
+    __shared__ __attribute__((aligned(16))) __bf16 s_dz[kTile * kHid];             // bf16 dZ of the current layer
     __shared__ float s_lg[kTile * kOut];
     __shared__ float s_red[256];
     __shared__ float s_colsum[4 * kHid];
