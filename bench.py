@@ -51,6 +51,12 @@ def parse():
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-lpt", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the proposal network and report variance x GPU-seconds, "
+                         "learned vs plain, for dissociation of H2(v=4,j=0)+Ca at 5e4 K")
+    ap.add_argument("--learned-replicates", type=int, default=16)
+    ap.add_argument("--learned-n", type=int, default=200_000)
+    ap.add_argument("--learned-epochs", type=int, default=20)
     return ap.parse_args()
 
 
@@ -188,9 +194,38 @@ def main():
         "labels": np.bincount(lab, minlength=6).tolist(),
         "wall_s": wall,
     }
+    if args.learned:
+        res["learned"] = learned_metric(args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_stride, args.cpu_procs)
     print(json.dumps(res), flush=True)
+
+
+def learned_metric(args):
+    """Train on 2e5 trajectories of the batched workload (GPU), then compare
+    the dissociation cross section's variance x GPU-seconds, plain against
+    importance-sampled, over seeded replicates."""
+    import qcams_workloads as W
+    import paper_2304_02731_amd as Q
+    from paper_2304_02731_amd import learned as L
+    tw = W.config_learned_train()
+    tr = L.train_network(tw.system, tw.params, tw.instances, epochs=args.learned_epochs)
+    print("learned: trained (%d rows, %.2f s data, %.2f s training, val CE %.4f, prior CE %.4f)"
+          % (tr.n_train, tr.data_s, tr.train_s, tr.val_loss, tr.prior_loss), file=sys.stderr,
+          flush=True)
+    tgt = W.config_learned_target(n_traj=args.learned_n).instances[0]
+    c = L.compare(tw.system, tw.params, tgt, None if tr.fallback else tr.net, channel=Q.DISS,
+                  n=args.learned_n, replicates=args.learned_replicates)
+    return {"metric": "var(sigma_diss) x GPU-s, plain / learned", "value": c.efficiency,
+            "target": "H2(v=4,j=0)+Ca, 5e4 K, b by area to 10 a0, dissociation",
+            "n_per_replicate": args.learned_n, "replicates": args.learned_replicates,
+            "sigma_plain": float(c.sigma_plain[Q.DISS]), "sigma_learned": float(c.sigma_is[Q.DISS]),
+            "var_plain": c.var_plain, "var_learned": c.var_is, "gpu_s_plain": c.gpu_s_plain,
+            "gpu_s_learned": c.gpu_s_is, "proposal_build_s": c.proposal_s, "ess_per_draw": c.ess,
+            "fallback_to_plain": c.fallback, "train_rows": tr.n_train,
+            "train_loss_first_last": [tr.train_loss[0], tr.train_loss[-1]],
+            "val_ce": tr.val_loss, "prior_ce": tr.prior_loss, "train_s": tr.train_s,
+            "data_s": tr.data_s}
 
 
 if __name__ == "__main__":

@@ -157,7 +157,7 @@ def test_features_and_labels(Q, torch, orc):
     x = x.cpu().numpy()
     y = y.cpu().numpy()
     s = buf["sample"].cpu().numpy()
-    lab = buf["outcome"].label.cpu().numpy()
+    lab = buf["outcome"].label.cpu().numpy().astype(np.int32)
     I = wl.instances[0]
     assert np.allclose(x[:, 0], (math.log10(I.Ec_K) - 3) / 2, atol=1e-6)
     assert np.allclose(x[:, 1], s[0] / 10.0, atol=1e-6)
@@ -245,3 +245,25 @@ def test_weighted_estimator_is_unbiased(Q, torch):
         assert abs(xs_p[15 + c] - xs_i[15 + c]) <= 3 * comb + 1e-12, (c, xs_p[15 + c], xs_i[15 + c], comb)
     print("sigma plain", xs_p[15:19], "+-", xs_p[19:23])
     print("sigma IS   ", xs_i[15:19], "+-", xs_i[19:23])
+
+
+def test_learned_pipeline_end_to_end(Q, torch):
+    """Train on a reduced training workload, build the dissociation proposal
+    for H2(v=4, j=0) + Ca at 5e4 K, and check that the importance-sampled
+    cross section agrees with plain sampling (unbiased) with weights bounded
+    by 1/alpha."""
+    from paper_2304_02731_amd import learned as L
+    wl = W.config_learned_train(per_inst=256)
+    tr = L.train_network(wl.system, wl.params, wl.instances, epochs=8, batch=1024, lr=2e-3)
+    assert tr.train_loss[-1] < tr.train_loss[0]
+    assert np.isfinite(tr.val_loss)
+    tgt = W.config_learned_target(n_traj=20000).instances[0]
+    cmp = L.compare(wl.system, wl.params, tgt, tr.net, channel=Q.DISS, n=20000, replicates=4,
+                    alpha=0.1)
+    print("train loss", np.round(tr.train_loss, 4), "val", tr.val_loss, "prior", tr.prior_loss)
+    print("ess", cmp.ess, "efficiency", cmp.efficiency, "sigma plain", cmp.sigma_plain,
+          "IS", cmp.sigma_is)
+    assert 0.0 < cmp.ess <= 1.0
+    # replicate means agree within 3 combined standard errors of the means
+    se = math.sqrt(cmp.var_plain / 4 + cmp.var_is / 4)
+    assert abs(cmp.sigma_plain[Q.DISS] - cmp.sigma_is[Q.DISS]) <= 3 * se + 1e-12
