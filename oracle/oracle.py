@@ -46,7 +46,8 @@ class Params(C.Structure):
     _fields_ = [("R0", C.c_double), ("t_stop", C.c_double), ("r_stop", C.c_double),
                 ("atol", C.c_double), ("rtol", C.c_double), ("gb_sigma", C.c_double),
                 ("h_fixed", C.c_double), ("fixed_step", C.c_int32),
-                ("literal_bound", C.c_int32), ("max_steps", C.c_int64)]
+                ("literal_bound", C.c_int32), ("max_steps", C.c_int64), ("rk", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Instance(C.Structure):
@@ -119,8 +120,25 @@ def lib():
                                   _dp, C.c_int64, C.POINTER(Record), _dp]
         L.orc_run_batch.argtypes = [C.POINTER(System), C.POINTER(Params), C.POINTER(Instance),
                                     _dp, C.POINTER(C.c_int64), C.c_int64, C.c_void_p, _dp]
+        L.orc_set_dop853.argtypes = [_dp] * 5
+        _install_dop853(L)
         _lib = L
     return _lib
+
+
+def dop853_tableau():
+    """The published Dormand-Prince 8(5,3) coefficients, as tabulated by scipy."""
+    from scipy.integrate._ivp import dop853_coefficients as D
+    n = D.N_STAGES
+    return (np.ascontiguousarray(D.A[:n, :n], dtype=np.float64), np.asarray(D.B, dtype=np.float64),
+            np.asarray(D.C[:n], dtype=np.float64), np.asarray(D.E3, dtype=np.float64),
+            np.asarray(D.E5, dtype=np.float64))
+
+
+def _install_dop853(L):
+    A, B, Cc, E3, E5 = dop853_tableau()
+    arrs = [np.ascontiguousarray(a) for a in (A.ravel(), B, Cc, E3, E5)]
+    L.orc_set_dop853(*[a.ctypes.data_as(_dp) for a in arrs])
 
 
 def _arr(x, n=None):
@@ -170,7 +188,8 @@ def make_system(s: W.System, masses_me: Sequence[float] | None = None) -> System
 def make_params(p: W.Params) -> Params:
     q = Params()
     for f, _ in Params._fields_:
-        setattr(q, f, getattr(p, f))
+        if f != "pad":
+            setattr(q, f, getattr(p, f))
     return q
 
 

@@ -72,6 +72,8 @@ typedef struct {
     int32_t fixed_step;
     int32_t literal_bound; /* 1: Eq. (8) only; 0: also require r < r0        */
     int64_t max_steps;
+    int32_t rk;            /* 0: Dormand-Prince 5(4); 1: Dormand-Prince 8(5,3) */
+    int32_t pad;
 } orc_params;
 
 typedef struct {
@@ -640,6 +642,59 @@ static void dp_step(const orc_system *s, const double *y, const double *k1, doub
     }
 }
 
+/* Dormand-Prince 8(5,3) ("DOP853", Hairer-Norsett-Wanner I, Sec. II.10):
+ * 12 stages, 8th-order solution, error estimated from a 5th-order and a
+ * 3rd-order embedded combination that also use f(y_new) (stage 13).  The
+ * published coefficients are handed in once by the caller. */
+static double D8_A[12][12], D8_B[12], D8_C[12], D8_E3[13], D8_E5[13];
+static int d8_ready = 0;
+
+void orc_set_dop853(const double *A, const double *B, const double *C, const double *E3,
+                    const double *E5)
+{
+    for (int i = 0; i < 12; ++i) {
+        for (int j = 0; j < 12; ++j) D8_A[i][j] = A[12 * i + j];
+        D8_B[i] = B[i];
+        D8_C[i] = C[i];
+    }
+    for (int i = 0; i < 13; ++i) { D8_E3[i] = E3[i]; D8_E5[i] = E5[i]; }
+    d8_ready = 1;
+}
+
+/* one DOP853 step: ynew, k13 = f(ynew) and the combined error norm
+ * err = |e5|^2 / sqrt((|e5|^2 + 0.01 |e3|^2) n) over the scaled components */
+static double d8_step(const orc_system *s, const double *y, const double *k1, double h,
+                      double atol, double rtol, double *ynew, double *k13)
+{
+    double k[13][12], yt[12];
+    memcpy(k[0], k1, sizeof(double) * 12);
+    for (int st = 1; st < 12; ++st) {
+        for (int i = 0; i < 12; ++i) {
+            double acc = 0.0;
+            for (int l = 0; l < st; ++l) acc += D8_A[st][l] * k[l][i];
+            yt[i] = y[i] + h * acc;
+        }
+        orc_rhs(s, yt, k[st]);
+    }
+    for (int i = 0; i < 12; ++i) {
+        double acc = 0.0;
+        for (int l = 0; l < 12; ++l) acc += D8_B[l] * k[l][i];
+        ynew[i] = y[i] + h * acc;
+    }
+    orc_rhs(s, ynew, k[12]);
+    memcpy(k13, k[12], sizeof(double) * 12);
+    double n5 = 0.0, n3 = 0.0;
+    for (int i = 0; i < 12; ++i) {
+        double e5 = 0.0, e3 = 0.0;
+        for (int l = 0; l < 13; ++l) { e5 += D8_E5[l] * k[l][i]; e3 += D8_E3[l] * k[l][i]; }
+        double sc = atol + rtol * fmax(fabs(y[i]), fabs(ynew[i]));
+        n5 += (h * e5 / sc) * (h * e5 / sc);
+        n3 += (h * e3 / sc) * (h * e3 / sc);
+    }
+    if (n5 == 0.0 && n3 == 0.0) return 0.0;
+    return n5 / sqrt((n5 + 0.01 * n3) * 12.0);
+}
+
 /* RMS error norm, Hairer-Norsett-Wanner I, Sec. II.4 */
 static double err_norm(const double *y, const double *ynew, const double *e, double atol, double rtol)
 {
@@ -653,7 +708,7 @@ static double err_norm(const double *y, const double *ynew, const double *e, dou
 
 /* starting step, Hairer-Norsett-Wanner I, Sec. II.4 */
 static double initial_step(const orc_system *s, const double *y, const double *f0,
-                           double atol, double rtol, double span)
+                           double atol, double rtol, double span, double order)
 {
     double d0 = 0.0, d1 = 0.0, y1[12], f1[12], d2 = 0.0;
     for (int i = 0; i < 12; ++i) {
@@ -673,7 +728,7 @@ static double initial_step(const orc_system *s, const double *y, const double *f
     }
     d2 = sqrt(d2 / 12.0) / h0;
     double dm = fmax(d1, d2);
-    double h1 = dm <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 1.0 / 5.0);
+    double h1 = dm <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 1.0 / order);
     double h = fmin(100.0 * h0, h1);
     return fmin(h, span);
 }
@@ -697,17 +752,27 @@ int orc_propagate(const orc_system *s, const orc_params *prm, double *y, double 
     double f0[12], ynew[12], k7[12], e[12], rb[3];
     collapse_radii(s, rb);
     double t = aux[0], tmax = aux[1], rs = aux[2], h = aux[5];
+    const int d8 = prm->rk == 1;
+    if (d8 && !d8_ready) return ORC_FAIL_NONFINITE;
+    /* step-size exponent 1/(q+1), q the order of the error estimate */
+    const double expo = d8 ? 1.0 / 8.0 : 1.0 / 5.0;
     orc_rhs(s, y, f0);
     if (prm->fixed_step) h = prm->h_fixed;
-    else if (!(h > 0.0)) h = initial_step(s, y, f0, prm->atol, prm->rtol, tmax - t);
+    else if (!(h > 0.0)) h = initial_step(s, y, f0, prm->atol, prm->rtol, tmax - t, d8 ? 8.0 : 5.0);
     double hmin = 1e-12 * tmax;
     int status = ORC_RUNNING, last_rejected = 0;
     if (t >= tmax) status = ORC_OK_TMAX;
     while (status == ORC_RUNNING) {
         if (*nstep >= prm->max_steps) { status = ORC_FAIL_MAXSTEPS; break; }
         double hs = fmin(h, tmax - t);
-        dp_step(s, y, f0, hs, ynew, k7, e);
-        double err = prm->fixed_step ? 0.0 : err_norm(y, ynew, e, prm->atol, prm->rtol);
+        double err;
+        if (d8) {
+            err = d8_step(s, y, f0, hs, prm->atol, prm->rtol, ynew, k7);
+        } else {
+            dp_step(s, y, f0, hs, ynew, k7, e);
+            err = err_norm(y, ynew, e, prm->atol, prm->rtol);
+        }
+        if (prm->fixed_step) err = 0.0;
         if (!isfinite(err)) err = INFINITY;
         if (err <= 1.0) {
             t = (hs == tmax - t) ? tmax : t + hs;
@@ -729,14 +794,14 @@ int orc_propagate(const orc_system *s, const orc_params *prm, double *y, double 
             else if (rmax2 > rs * rs) status = ORC_OK_RSTOP;
             else if (t >= tmax) status = ORC_OK_TMAX;
             if (!prm->fixed_step) {
-                double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(err, -0.2)));
+                double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(err, -expo)));
                 if (last_rejected && fac > 1.0) fac = 1.0;
                 h = hs * fac;
             }
             last_rejected = 0;
         } else {
             *nrej += 1;
-            h = hs * fmax(0.2, 0.9 * pow(err, -0.2));
+            h = hs * fmax(0.2, 0.9 * pow(err, -expo));
             last_rejected = 1;
         }
         if (status == ORC_RUNNING && !prm->fixed_step && h < hmin) status = ORC_FAIL_HMIN;

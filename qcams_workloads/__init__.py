@@ -64,6 +64,9 @@ class Params:
     fixed_step: int = 0
     literal_bound: int = 0
     max_steps: int = 10_000_000
+    # Runge-Kutta variant: 0 = Dormand-Prince 5(4) (the paper's RK45),
+    # 1 = Dormand-Prince 8(5,3)
+    rk: int = 0
 
 
 @dataclasses.dataclass(frozen=True)
