@@ -5,7 +5,8 @@ One step = one pass of the whole path over the batched H2 + Ca workload
 (96 instances: 16 collision energies 1e3..1e5 K x v in {0,2,4} x j in {0,5},
 1042 trajectories each, b uniform in area to 10 a0; 100,032 trajectories):
 instance set-up with Bohr-Sommerfeld levels, initial conditions, adaptive
-RK5(4) propagation of every trajectory to its stop rule, classification and
+Runge-Kutta propagation (Dormand-Prince 5(4), the paper's integrator, or the
+8(5,3) variant) of every trajectory to its stop rule, classification and
 Gaussian binning, per-instance cross sections and rates.  All inputs are
 synthetic and seeded; nothing is cached between steps.
 
@@ -15,6 +16,7 @@ CPU-oracle baseline on a bounded sample).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -25,10 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# FP64 operations per RK5(4) trial step of one trajectory on the all-Morse
-# surface (FMA = 2), counted from the propagation kernel's instruction
-# stream; see the measurement section of the design notes.
-F_STEP_MORSE = 1969.4
+# FP64 operations per trial step of one trajectory on the all-Morse surface
+# (FMA = 2), counted with hardware FP64 instruction counters on a full-wave
+# fixed-step run of the propagation kernel, per RK variant.
+F_STEP_MORSE = {0: 1969.4, 1: 4342.4}
+RK_NAMES = {"dopri5": 0, "dop853": 1}
 PEAK_FP64_VECTOR = 78.6e12   # MI355X, FLOP/s
 
 
@@ -42,6 +45,8 @@ def parse():
                     help="CPU baseline runs every k-th trajectory id through the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-procs", type=int, default=16)
+    ap.add_argument("--rk", default="dop853", choices=list(RK_NAMES),
+                    help="Runge-Kutta variant of the adaptive integrator")
     ap.add_argument("--path", default="run", choices=["run", "unfused"],
                     help="run: fused persistent launch (qcams_run); unfused: the four ABI calls")
     ap.add_argument("--autotune", action="store_true",
@@ -94,6 +99,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     wl = W.config_batched() if args.workload == "batched" else W.config_small()
+    rk = RK_NAMES[args.rk]
+    wl.params = dataclasses.replace(wl.params, rk=rk)
     dev = torch.device("cuda", 0)
     ctx = Q.Context(wl.system, wl.params, device=0)
     ctx.set_instances(wl.instances)
@@ -157,8 +164,8 @@ def main():
     nrej = st.nrej.cpu().numpy().astype(np.int64)
     per_traj = nstep + nrej
     trial_steps = int(per_traj.sum())
-    flops = trial_steps * F_STEP_MORSE
-    achieved = flops / (prop_ms * 1e-3) / 1e12
+    f_step = F_STEP_MORSE[rk]
+    achieved = trial_steps * f_step / (prop_ms * 1e-3) / 1e12 if f_step else None
     lab = out.label.cpu().numpy()
     dE = out.d[3].cpu().numpy()
     fin = lab != Q.FAILED
@@ -176,15 +183,17 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "n_traj": n, "instances": len(wl.instances),
-                   "surface": "H2+Ca all-Morse", "atol": wl.params.atol,
+                   "surface": "H2+Ca all-Morse", "integrator": args.rk, "atol": wl.params.atol,
                    "rtol": wl.params.rtol, "R0": wl.params.R0, "t_stop": wl.params.t_stop,
                    "r_stop": wl.params.r_stop},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_FP64_VECTOR,
+                     "unit": "TFLOP/s",
+                     "frac": achieved * 1e12 / PEAK_FP64_VECTOR if achieved else None,
                      "traffic": None,
-                     "kernel": "k_persistent<0,0,0>" if args.path == "run" else "k_propagate<0,0,0>",
+                     "kernel": ("k_persistent<0,0,0,%d>" if args.path == "run"
+                                else "k_propagate<0,0,0,%d>") % rk,
                      "timed_ms": prop_ms, "trial_steps": trial_steps,
-                     "flop_per_trial_step": F_STEP_MORSE},
+                     "flop_per_trial_step": f_step},
         "path": args.path, "run_opts": opts.as_dict(), "autotune": tuned,
         "trial_steps_per_s": trial_steps / (ms_step * 1e-3),
         "trial_steps_per_traj": {q: int(np.percentile(per_traj, p)) for q, p in

@@ -100,7 +100,13 @@ typedef struct {
     int32_t fixed_step;    /* 1: no error control, step h_fixed */
     int32_t literal_bound; /* 1: Eq. (8) alone; 0: also require the pair inside its barrier */
     int64_t max_steps;     /* accepted steps per trajectory, 1 .. 2^31-1 */
+    int32_t rk;            /* QCAMS_RK_DOPRI5 (the paper's RK45) or QCAMS_RK_DOP853 */
+    int32_t pad;
 } qcams_params;
+
+/* ---- Runge-Kutta variants of the adaptive integrator ---- */
+#define QCAMS_RK_DOPRI5 0 /* Dormand-Prince 5(4): controller exponent 1/5 */
+#define QCAMS_RK_DOP853 1 /* Dormand-Prince 8(5,3): exponent 1/8, Hairer's combined error */
 
 typedef struct {
     double Ec_K;       /* collision energy (kelvin) */
@@ -225,7 +231,7 @@ typedef struct {
     int32_t check_every; /* trial steps between refill checks (0 = 1) */
     int32_t lpt;         /* 1: start instances longest-expected-first (cost ~ 1/(v_c tau_vj)) */
     int32_t graph;       /* 1: capture the launch sequence once per buffer set and replay it */
-    int32_t pad;
+    int32_t rk;          /* 0: the context's variant; 1: DOPRI5; 2: DOP853 */
 } qcams_run_opts;
 
 /* The whole hot path over every installed trajectory (N = sum of n_traj):
@@ -256,10 +262,16 @@ int qcams_last_run_kernel_ms(qcams_ctx *ctx, double *ms);
  * installed instances -- install a calibration subset first -- and return
  * the fastest in *best (graph off) with its time in *best_ms (may be NULL).
  * Buffers as for qcams_run; each option is run `reps` times and the minimum
- * kept.  sync.  Errors as qcams_run. */
-
+ * kept.  With search_rk = 1 the RK variant is chosen first: DOPRI5 and
+ * DOP853 are each run with the default schedule and the faster of those
+ * whose largest |H(t_f) - H(0)| / escale over non-failed trajectories is
+ * below energy_gate (<= 0: no gate) is kept (best->rk = 1 or 2); the
+ * variant changes per-trajectory results, the schedule does not.  With
+ * search_rk = 0 the context's variant is used (best->rk = 0).  sync.
+ * Errors as qcams_run; EINVAL also when no variant keeps the gate. */
 int qcams_autotune(qcams_ctx *ctx, const qcams_state *st, const qcams_outcome *out, int64_t *ids,
-                   double *xs, int32_t reps, qcams_run_opts *best, double *best_ms);
+                   double *xs, int32_t reps, int32_t search_rk, double energy_gate,
+                   qcams_run_opts *best, double *best_ms);
 
 /* ======================================================================
  * Learned importance-sampling proposal.

@@ -109,7 +109,7 @@ __device__ inline int find_instance(const Inst* inst, int n_inst, int64_t id)
     return k;
 }
 
-template <int K0, int K1, int K2>
+template <int K0, int K1, int K2, int RK>
 __global__ void __launch_bounds__(256)
 k_init(Sys S, Prm P, const Inst* inst, int n_inst, const int64_t* ids, int64_t n, double* d,
        int32_t* nstep, int32_t* nrej, uint8_t* status, int64_t ld, double* sample,
@@ -134,7 +134,7 @@ k_init(Sys S, Prm P, const Inst* inst, int n_inst, const int64_t* ids, int64_t n
         if (st == RUNNING) {
             double F[6], s2[3];
             force<K0, K1, K2>(S, x, F, s2);
-            h = P.fixed_step ? P.h_fixed : initial_step<K0, K1, K2>(S, x, p, F, P.atol, P.rtol, tmax);
+            h = P.fixed_step ? P.h_fixed : initial_step<K0, K1, K2, RK>(S, x, p, F, P.atol, P.rtol, tmax);
         }
     }
 #pragma unroll
@@ -158,7 +158,7 @@ k_init(Sys S, Prm P, const Inst* inst, int n_inst, const int64_t* ids, int64_t n
 // ---------------------------------------------------------------------------
 // propagation: one trajectory per lane until it stops
 // ---------------------------------------------------------------------------
-template <int K0, int K1, int K2>
+template <int K0, int K1, int K2, int RK>
 __global__ void __launch_bounds__(256) k_propagate(Sys S, Prm P, double* d, int32_t* nstep,
                                                    int32_t* nrej, uint8_t* status, int64_t ld,
                                                    int64_t n)
@@ -185,11 +185,11 @@ __global__ void __launch_bounds__(256) k_propagate(Sys S, Prm P, double* d, int3
     force<K0, K1, K2>(S, L.x, L.F, s2);
     if (P.fixed_step) L.h = P.h_fixed;
     else if (!(L.h > 0.0))
-        L.h = initial_step<K0, K1, K2>(S, L.x, L.p, L.F, P.atol, P.rtol, L.tmax - L.t);
+        L.h = initial_step<K0, K1, K2, RK>(S, L.x, L.p, L.F, P.atol, P.rtol, L.tmax - L.t);
     if (!is_finite(L.t) || !is_finite(L.tmax) || !is_finite(L.h)) L.status = FAIL_NONFINITE;
     else if (L.t >= L.tmax) L.status = OK_TMAX;
     else if (L.nstep >= P.max_steps) L.status = FAIL_MAXSTEPS;
-    while (L.status == RUNNING) lane_step<K0, K1, K2>(S, P, L);
+    while (L.status == RUNNING) lane_step<K0, K1, K2, RK>(S, P, L);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         d[f * ld + i] = L.x[f];
@@ -242,7 +242,7 @@ __global__ void k_run_tables(const Inst* inst, int n_inst, const int32_t* ord_in
     ids[pos] = inst[k].first_id + local;
 }
 
-template <int K0, int K1, int K2>
+template <int K0, int K1, int K2, int RK>
 __global__ void __launch_bounds__(256)
 k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min, int check_every,
              double* d, int32_t* nstep, int32_t* nrej, uint8_t* status, int64_t ld)
@@ -298,7 +298,7 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
         if (__ballot(active) == 0ull) break;
         // ---- integrate ----
         for (int s = 0; s < check_every; ++s) {
-            if (active && L.status == RUNNING) lane_step<K0, K1, K2>(S, P, L);
+            if (active && L.status == RUNNING) lane_step<K0, K1, K2, RK>(S, P, L);
         }
         // ---- retire finished lanes ----
         if (active && L.status != RUNNING) {
@@ -578,38 +578,64 @@ static bool pair_ok(const qcams_pair& p)
 
 static bool pot_is_zero(const qcams_pair& p) { return p.kind == QCAMS_MORSE && p.p[0] == 0.0; }
 
-template <int K0, int K1, int K2>
-static void launch_propagate(qcams_ctx* c, const qcams_state* st, int64_t n, hipStream_t s)
+// Kernels are specialised for the all-Morse and the LJ/Morse/Buckingham pair
+// triples (other triples select the pair kind at run time) and for the RK
+// variant; `with_kinds` maps the context to the instantiation.
+template <template <int, int, int, int> class L, int RK, class... A>
+static void with_kinds(const qcams_ctx* c, A&&... a)
 {
-    hipLaunchKernelGGL((k_propagate<K0, K1, K2>), dim3(grid_of(n, 256)), dim3(256), 0, s, c->sys,
-                       c->prm, st->d, st->nstep, st->nrej, st->status, st->ld, n);
+    if (c->kinds == 0) L<0, 0, 0, RK>::go(a...);
+    else if (c->kinds == QCAMS_LJ + 3 * QCAMS_MORSE + 9 * QCAMS_BUCK) L<1, 0, 2, RK>::go(a...);
+    else L<-1, -1, -1, RK>::go(a...);
 }
 
-template <int K0, int K1, int K2>
-static void launch_persistent(qcams_ctx* c, int blocks, int refill_min, int check_every,
-                              const int64_t* order, const qcams_state* st, hipStream_t s)
+template <template <int, int, int, int> class L, class... A>
+static void with_variant(const qcams_ctx* c, int rk, A&&... a)
 {
-    RunMap M{order, c->n_total};
-    hipLaunchKernelGGL((k_persistent<K0, K1, K2>), dim3(blocks), dim3(256), 0, s, c->sys, c->prm,
-                       M, c->d_counter, refill_min, check_every, st->d, st->nstep, st->nrej,
-                       st->status, st->ld);
+    if (rk == 1) with_kinds<L, 1>(c, a...);
+    else with_kinds<L, 0>(c, a...);
 }
 
-template <int K0, int K1, int K2>
-static void launch_init(qcams_ctx* c, const int64_t* ids, int64_t n, const qcams_state* st,
-                        double* sample, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_init<K0, K1, K2>), dim3(grid_of(n, 256)), dim3(256), 0, s, c->sys, c->prm,
-                       c->d_inst, c->n_inst, ids, n, st->d, st->nstep, st->nrej, st->status,
-                       st->ld, sample, (const double*)c->d_prop_q, (const double*)c->d_prop_cdf);
-}
+template <int K0, int K1, int K2, int RK>
+struct PropagateL {
+    static void go(qcams_ctx* c, const qcams_state* st, int64_t n, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_propagate<K0, K1, K2, RK>), dim3(grid_of(n, 256)), dim3(256), 0, s,
+                           c->sys, c->prm, st->d, st->nstep, st->nrej, st->status, st->ld, n);
+    }
+};
 
-static void dispatch_init(qcams_ctx* c, const int64_t* ids, int64_t n, const qcams_state* st,
-                          double* sample, hipStream_t s)
+template <int K0, int K1, int K2, int RK>
+struct PersistentL {
+    static void go(qcams_ctx* c, int blocks, int refill_min, int check_every, const int64_t* order,
+                   const qcams_state* st, hipStream_t s)
+    {
+        RunMap M{order, c->n_total};
+        Prm P = c->prm;
+        P.rk = RK;
+        hipLaunchKernelGGL((k_persistent<K0, K1, K2, RK>), dim3(blocks), dim3(256), 0, s, c->sys, P,
+                           M, c->d_counter, refill_min, check_every, st->d, st->nstep, st->nrej,
+                           st->status, st->ld);
+    }
+};
+
+template <int K0, int K1, int K2, int RK>
+struct InitL {
+    static void go(qcams_ctx* c, const int64_t* ids, int64_t n, const qcams_state* st,
+                   double* sample, hipStream_t s)
+    {
+        Prm P = c->prm;
+        P.rk = RK;
+        hipLaunchKernelGGL((k_init<K0, K1, K2, RK>), dim3(grid_of(n, 256)), dim3(256), 0, s, c->sys,
+                           P, c->d_inst, c->n_inst, ids, n, st->d, st->nstep, st->nrej, st->status,
+                           st->ld, sample, (const double*)c->d_prop_q, (const double*)c->d_prop_cdf);
+    }
+};
+
+static void dispatch_init(qcams_ctx* c, int rk, const int64_t* ids, int64_t n,
+                          const qcams_state* st, double* sample, hipStream_t s)
 {
-    if (c->kinds == 0) launch_init<0, 0, 0>(c, ids, n, st, sample, s);
-    else if (c->kinds == QCAMS_LJ + 3 * QCAMS_MORSE + 9 * QCAMS_BUCK) launch_init<1, 0, 2>(c, ids, n, st, sample, s);
-    else launch_init<-1, -1, -1>(c, ids, n, st, sample, s);
+    with_variant<InitL>(c, rk, c, ids, n, st, sample, s);
 }
 
 extern "C" {
@@ -625,7 +651,8 @@ int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qca
             return fail(nullptr, QCAMS_EINVAL, "pair %d: unsupported kind or parameters", i);
     if (!(prm->atol > 0.0) || !(prm->rtol >= 0.0) || !(prm->t_stop > 0.0) || !(prm->r_stop > 0.0) ||
         !(prm->R0 > 0.0) || !(prm->gb_sigma > 0.0) || prm->max_steps < 1 ||
-        prm->max_steps > 2147483647LL || (prm->fixed_step && !(prm->h_fixed > 0.0)))
+        prm->max_steps > 2147483647LL || (prm->fixed_step && !(prm->h_fixed > 0.0)) ||
+        (prm->rk != 0 && prm->rk != 1))
         return fail(nullptr, QCAMS_EINVAL, "invalid integration parameters");
     qcams_ctx* c = new (std::nothrow) qcams_ctx();
     if (!c) return fail(nullptr, QCAMS_ENOMEM, "host allocation failed");
@@ -709,6 +736,8 @@ int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qca
     c->prm.fixed_step = prm->fixed_step;
     c->prm.literal_bound = prm->literal_bound;
     c->prm.max_steps = prm->max_steps;
+    c->prm.rk = prm->rk;
+    c->prm.pad = 0;
     *out = c;
     return rc;
 }
@@ -878,7 +907,7 @@ int qcams_init_conditions(qcams_ctx* c, const int64_t* ids, int64_t n, const qca
     if (n == 0) return QCAMS_OK;
     if (!ids) return fail(c, QCAMS_EINVAL, "null ids");
     HIP_OK(c, hipSetDevice(c->device));
-    dispatch_init(c, ids, n, st, sample, (hipStream_t)stream);
+    dispatch_init(c, c->prm.rk, ids, n, st, sample, (hipStream_t)stream);
     HIP_OK(c, hipGetLastError());
     return QCAMS_OK;
 }
@@ -890,9 +919,7 @@ int qcams_propagate(qcams_ctx* c, const qcams_state* st, int64_t n, void* stream
     if (n == 0) return QCAMS_OK;
     HIP_OK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    if (c->kinds == 0) launch_propagate<0, 0, 0>(c, st, n, s);
-    else if (c->kinds == QCAMS_LJ + 3 * QCAMS_MORSE + 9 * QCAMS_BUCK) launch_propagate<1, 0, 2>(c, st, n, s);
-    else launch_propagate<-1, -1, -1>(c, st, n, s);
+    with_variant<PropagateL>(c, c->prm.rk, c, st, n, s);
     HIP_OK(c, hipGetLastError());
     return QCAMS_OK;
 }
@@ -932,6 +959,12 @@ int qcams_cross_sections(qcams_ctx* c, const qcams_outcome* out, const int64_t* 
 // ---------------------------------------------------------------------------
 // fused persistent run, launch-graph capture, autotuning
 // ---------------------------------------------------------------------------
+// RK variant of a run: the option overrides the context's parameter
+static int run_variant(const qcams_ctx* c, const qcams_run_opts* o)
+{
+    return o->rk == 1 ? 0 : (o->rk == 2 ? 1 : c->prm.rk);
+}
+
 // The run is three launch groups: the small set-up kernels (work order,
 // initial conditions, counter reset), the persistent propagation kernel, and
 // the small analysis kernels (classification, reduction).  In graph mode the
@@ -945,7 +978,7 @@ static void enqueue_pre(qcams_ctx* c, const qcams_run_opts* o, const qcams_state
     hipLaunchKernelGGL(k_run_tables, dim3(grid_of(n, 256)), dim3(256), 0, s, c->d_inst, c->n_inst,
                        lpt ? c->d_lpt_inst : c->d_id_inst, lpt ? c->d_lpt_off : c->d_nat_off,
                        c->d_nat_off, n, ids, c->d_order);
-    dispatch_init(c, ids, n, st, sample, s);
+    dispatch_init(c, run_variant(c, o), ids, n, st, sample, s);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, c->d_counter);
 }
 
@@ -956,10 +989,7 @@ static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const qcams
     const int rm = o->refill_min < 1 ? 1 : (o->refill_min > 64 ? 64 : o->refill_min);
     const int ce = o->check_every < 1 ? 1 : o->check_every;
     if (hipEventRecord(c->ev_prop[0], s) != hipSuccess) return QCAMS_EHIP;
-    if (c->kinds == 0) launch_persistent<0, 0, 0>(c, blocks, rm, ce, c->d_order, st, s);
-    else if (c->kinds == QCAMS_LJ + 3 * QCAMS_MORSE + 9 * QCAMS_BUCK)
-        launch_persistent<1, 0, 2>(c, blocks, rm, ce, c->d_order, st, s);
-    else launch_persistent<-1, -1, -1>(c, blocks, rm, ce, c->d_order, st, s);
+    with_variant<PersistentL>(c, run_variant(c, o), c, blocks, rm, ce, (const int64_t*)c->d_order, st, s);
     if (hipEventRecord(c->ev_prop[1], s) != hipSuccess) return QCAMS_EHIP;
     return hipGetLastError() == hipSuccess ? QCAMS_OK : QCAMS_EHIP;
 }
@@ -1007,8 +1037,8 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
     o.lpt = 1;
     o.graph = 0;
     if (opts) o = *opts;
-    if (o.blocks < 0 || o.refill_min < 0 || o.check_every < 0)
-        return fail(c, QCAMS_EINVAL, "negative run option");
+    if (o.blocks < 0 || o.refill_min < 0 || o.check_every < 0 || o.rk < 0 || o.rk > 2)
+        return fail(c, QCAMS_EINVAL, "invalid run option");
     for (const Inst& I : c->h_inst)
         if (I.b_mode == 2 && (!sample || !c->d_prop_q))
             return fail(c, QCAMS_EINVAL, "proposal instances need a sample buffer and a proposal");
@@ -1053,7 +1083,7 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
                               (uint64_t)st->status, (uint64_t)st->ld, (uint64_t)sample,
                               (uint64_t)out->label, (uint64_t)out->d, (uint64_t)out->ld,
                               (uint64_t)ids, (uint64_t)xs, (uint64_t)hist,
-                              (uint64_t)o.lpt,
+                              (uint64_t)o.lpt | ((uint64_t)o.rk << 8),
                               (uint64_t)out->vt ^ ((uint64_t)out->jt << 1),
                               (uint64_t)c->n_total ^ ((uint64_t)c->n_inst << 40)};
     if (memcmp(key, c->graph_key, sizeof key) != 0) {
@@ -1073,11 +1103,51 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
     return QCAMS_OK;
 }
 
+// One timed run (minimum over reps) of option set `o`.
+static int tune_time(qcams_ctx* c, const qcams_run_opts* o, const qcams_state* st,
+                     const qcams_outcome* out, int64_t* ids, double* xs, int reps, hipStream_t s,
+                     hipEvent_t e0, hipEvent_t e1, double* tmin)
+{
+    *tmin = 1e300;
+    for (int r = 0; r < reps; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) return QCAMS_EHIP;
+        int rc = qcams_run(c, o, st, nullptr, out, ids, xs, nullptr, s);
+        if (rc != QCAMS_OK) return rc;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return QCAMS_EHIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return QCAMS_EHIP;
+        *tmin = fmin(*tmin, (double)ms);
+    }
+    return QCAMS_OK;
+}
+
+// Largest |H(t_f) - H(0)| / escale over the trajectories of the last run that
+// did not fail (host copy of the outcome; the autotuner is synchronous).
+static int tune_energy(qcams_ctx* c, const qcams_outcome* out, double* worst)
+{
+    const int64_t n = c->n_total;
+    std::vector<double> dE((size_t)n);
+    std::vector<uint8_t> lab((size_t)n);
+    if (n > 0) {
+        if (hipMemcpy(dE.data(), out->d + 3 * out->ld, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(lab.data(), out->label, n, hipMemcpyDeviceToHost) != hipSuccess)
+            return QCAMS_EHIP;
+    }
+    double w = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (lab[(size_t)i] != QCAMS_FAILED) w = fmax(w, fabs(dE[(size_t)i]));
+    *worst = w;
+    return QCAMS_OK;
+}
+
 int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out, int64_t* ids,
-                   double* xs, int32_t reps, qcams_run_opts* best, double* best_ms)
+                   double* xs, int32_t reps, int32_t search_rk, double energy_gate,
+                   qcams_run_opts* best, double* best_ms)
 {
     if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
     if (!best) return fail(c, QCAMS_EINVAL, "null result");
+    if (search_rk != 0 && search_rk != 1) return fail(c, QCAMS_EINVAL, "search_rk must be 0 or 1");
     if (reps < 1) reps = 1;
     HIP_OK(c, hipSetDevice(c->device));
     hipStream_t s = nullptr;
@@ -1093,6 +1163,30 @@ int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out
         HIP_OK(c, hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device));
         c->n_cu = cu > 0 ? cu : 256;
     }
+    // Variant first (default schedule), among those that keep the energy gate;
+    // then the schedule for the chosen variant.  The variant changes results
+    // (a different integrator); the schedule does not.
+    int rk = 0;
+    if (search_rk) {
+        double tv = 1e300;
+        bool any = false;
+        for (int v = 1; v <= 2 && rc == QCAMS_OK; ++v) {
+            qcams_run_opts o{};
+            o.refill_min = 1;
+            o.check_every = 8;
+            o.lpt = 1;
+            o.rk = v;
+            double t = 0.0, worst = 0.0;
+            rc = tune_time(c, &o, st, out, ids, xs, reps, s, e0, e1, &t);
+            if (rc == QCAMS_OK) rc = tune_energy(c, out, &worst);
+            if (rc == QCAMS_OK && (energy_gate <= 0.0 || worst < energy_gate) && t < tv) {
+                tv = t;
+                rk = v;
+                any = true;
+            }
+        }
+        if (rc == QCAMS_OK && !any) rc = QCAMS_EINVAL;
+    }
     const int blocks_c[3] = {c->n_cu, 2 * c->n_cu, 4 * c->n_cu};
     const int refill_c[3] = {1, 8, 32};
     const int check_c[2] = {1, 8};
@@ -1106,16 +1200,9 @@ int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out
                     o.check_every = check_c[ci];
                     o.lpt = lpt;
                     o.graph = 0;
+                    o.rk = rk;
                     double tmin = 1e300;
-                    for (int r = 0; r < reps && rc == QCAMS_OK; ++r) {
-                        rc = hipEventRecord(e0, s) == hipSuccess ? QCAMS_OK : QCAMS_EHIP;
-                        if (rc == QCAMS_OK) rc = qcams_run(c, &o, st, nullptr, out, ids, xs, nullptr, s);
-                        if (rc == QCAMS_OK && hipEventRecord(e1, s) != hipSuccess) rc = QCAMS_EHIP;
-                        if (rc == QCAMS_OK && hipEventSynchronize(e1) != hipSuccess) rc = QCAMS_EHIP;
-                        float ms = 0.f;
-                        if (rc == QCAMS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = QCAMS_EHIP;
-                        if (rc == QCAMS_OK) tmin = fmin(tmin, (double)ms);
-                    }
+                    rc = tune_time(c, &o, st, out, ids, xs, reps, s, e0, e1, &tmin);
                     if (rc == QCAMS_OK && tmin < best_t) {
                         best_t = tmin;
                         bo = o;
@@ -1124,6 +1211,7 @@ int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(s);
+    if (rc == QCAMS_EINVAL) return fail(c, rc, "no RK variant keeps the energy gate");
     if (rc != QCAMS_OK) return rc == QCAMS_EHIP ? fail(c, rc, "autotune run failed") : rc;
     *best = bo;
     if (best_ms) *best_ms = best_t;

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dop853_tableau.h"
+
 #define QD __host__ __device__ inline
 
 namespace qd {
@@ -66,6 +68,7 @@ struct Prm {
     double R0, t_stop, r_stop, atol, rtol, gb_sigma, h_fixed;
     int32_t fixed_step, literal_bound;
     int64_t max_steps;
+    int32_t rk, pad;   // 0: Dormand-Prince 5(4); 1: Dormand-Prince 8(5,3)
 };
 
 // instance row as stored on the device (levels filled in at set-up)
@@ -154,12 +157,14 @@ QD double exp_cw(double x)
     return ldexp(p, (int)n);
 }
 
-// Step-size factor err^(-1/5) of the controller, in FP32 (a heuristic: its
-// value only shapes the step sequence, never the accuracy bound).
+// Step-size factor err^(-1/(q+1)) of the controller (q = 4 for the 5(4)
+// pair, 7 for the 8(5,3) one), in FP32: a heuristic whose value only shapes
+// the step sequence, never the accuracy bound.
+template <int RK>
 QD double ctrl_pow(double err)
 {
     const float l = __builtin_amdgcn_logf((float)err);   // log2
-    return (double)__builtin_amdgcn_exp2f(-0.2f * l);
+    return (double)__builtin_amdgcn_exp2f((RK == 1 ? -0.125f : -0.2f) * l);
 }
 
 QD void pot_morse(const Pot& P, double r, double& V, double& d1, double& d2)
@@ -403,9 +408,115 @@ QD double dopri5_trial(const Sys& S, const double* x, const double* p, const dou
     return sqrt(acc * (1.0 / 12.0));
 }
 
+// ---------------------------------------------------------------------------
+// Dormand-Prince 8(5,3), in the same separable form: with Q = A A,
+//   X_i = x + h c_i v + (h^2/mu) sum_l Q_il F_l,
+//   x'  = x + h v + (h^2/mu) sum_l (bA)_l F_l,     p' = p + h sum_l b_l F_l,
+// and the two error estimates (5th and 3rd order, using F_13 = F(x'))
+//   e_x = (h^2/mu) sum_l (E A + E_13 b)_l F_l,      e_p = h sum_l E_l F_l.
+// The combined norm |e5|^2 / sqrt((|e5|^2 + 0.01 |e3|^2) n) is Hairer's.
+// The derived coefficients are computed at compile time from the published
+// tableau; zero products are dropped by the compiler.
+// ---------------------------------------------------------------------------
+namespace d8 {
+constexpr int NS = 12;
+struct Derived {
+    double q[NS][NS];
+    double bA[NS], e5A[NS], e3A[NS];
+};
+constexpr Derived derive()
+{
+    Derived d{};
+    for (int i = 0; i < NS; ++i)
+        for (int l = 0; l < NS; ++l) {
+            double s = 0.0;
+            for (int j = 0; j < NS; ++j) s += d8tab::A[i * NS + j] * d8tab::A[j * NS + l];
+            d.q[i][l] = s;
+        }
+    for (int l = 0; l < NS; ++l) {
+        double b = 0.0, e5 = 0.0, e3 = 0.0;
+        for (int i = 0; i < NS; ++i) {
+            b += d8tab::B[i] * d8tab::A[i * NS + l];
+            e5 += d8tab::E5[i] * d8tab::A[i * NS + l];
+            e3 += d8tab::E3[i] * d8tab::A[i * NS + l];
+        }
+        d.bA[l] = b;
+        d.e5A[l] = e5 + d8tab::E5[NS] * d8tab::B[l];
+        d.e3A[l] = e3 + d8tab::E3[NS] * d8tab::B[l];
+    }
+    return d;
+}
+constexpr Derived T = derive();
+}  // namespace d8
+
+template <int K0, int K1, int K2>
+QD double dop853_trial(const Sys& S, const double* x, const double* p, const double* F1,
+                       double h, double atol, double rtol, double* xn, double* pn,
+                       double* F13, double* s2)
+{
+    using namespace d8;
+    double F[NS][6], junk[3];
+    const double hh = h * h;
+    const double im0 = S.inv_mu12, im1 = S.inv_mu123;
+    const double g0 = hh * im0, g1 = hh * im1;
+#define IM(i) ((i) < 3 ? im0 : im1)
+#define GG(i) ((i) < 3 ? g0 : g1)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) F[0][i] = F1[i];
+#pragma unroll
+    for (int st = 1; st < NS; ++st) {
+        double X[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < NS; ++l)
+                if (l < st && T.q[st][l] != 0.0) acc = fma(T.q[st][l], F[l][i], acc);
+            X[i] = fma(GG(i), acc, fma(h * d8tab::C[st] * IM(i), p[i], x[i]));
+        }
+        force<K0, K1, K2>(S, X, F[st], junk);
+    }
+    double ex5[6], ex3[6], ep5[6], ep3[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double sx = 0.0, sp = 0.0, a5 = 0.0, a3 = 0.0, b5 = 0.0, b3 = 0.0;
+#pragma unroll
+        for (int l = 0; l < NS; ++l) {
+            if (T.bA[l] != 0.0) sx = fma(T.bA[l], F[l][i], sx);
+            if (d8tab::B[l] != 0.0) sp = fma(d8tab::B[l], F[l][i], sp);
+            if (T.e5A[l] != 0.0) a5 = fma(T.e5A[l], F[l][i], a5);
+            if (T.e3A[l] != 0.0) a3 = fma(T.e3A[l], F[l][i], a3);
+            if (d8tab::E5[l] != 0.0) b5 = fma(d8tab::E5[l], F[l][i], b5);
+            if (d8tab::E3[l] != 0.0) b3 = fma(d8tab::E3[l], F[l][i], b3);
+        }
+        xn[i] = fma(GG(i), sx, fma(h * IM(i), p[i], x[i]));
+        pn[i] = fma(h, sp, p[i]);
+        ex5[i] = GG(i) * a5;
+        ex3[i] = GG(i) * a3;
+        ep5[i] = b5;
+        ep3[i] = b3;
+    }
+#undef IM
+#undef GG
+    force<K0, K1, K2>(S, xn, F13, s2);
+    double n5 = 0.0, n3 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const double e5p = h * fma(d8tab::E5[NS], F13[i], ep5[i]);
+        const double e3p = h * fma(d8tab::E3[NS], F13[i], ep3[i]);
+        const double isx = rcp_nr(fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol));
+        const double isp = rcp_nr(fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol));
+        const double a = ex5[i] * isx, b = e5p * isp, c = ex3[i] * isx, d = e3p * isp;
+        n5 = fma(a, a, fma(b, b, n5));
+        n3 = fma(c, c, fma(d, d, n3));
+    }
+    if (n5 == 0.0 && n3 == 0.0) return 0.0;
+    return n5 / sqrt((n5 + 0.01 * n3) * 12.0);
+}
+
 // Starting step (Hairer-Norsett-Wanner I, Sec. II.4), on the 12-component
 // system y = (x, p), f = (p/mu, F).
-template <int K0, int K1, int K2>
+template <int K0, int K1, int K2, int RK = 0>
 QD double initial_step(const Sys& S, const double* x, const double* p, const double* F0,
                        double atol, double rtol, double span)
 {
@@ -436,7 +547,7 @@ QD double initial_step(const Sys& S, const double* x, const double* p, const dou
     }
     d2 = sqrt(d2 / 12.0) / h0;
     const double dm = fmax(d1, d2);
-    const double h1 = dm <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 0.2);
+    const double h1 = dm <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, RK == 1 ? 0.125 : 0.2);
     return fmin(fmin(100.0 * h0, h1), span);
 }
 
@@ -456,13 +567,15 @@ struct Lane {
 // inside a Buckingham inner maximum).  Step control: accept iff err <= 1,
 // h <- h min(10, max(0.2, 0.9 err^-1/5)), no increase right after a rejection,
 // h_min = 1e-12 t_max.
-template <int K0, int K1, int K2>
+template <int K0, int K1, int K2, int RK = 0>
 QD void lane_step(const Sys& S, const Prm& P, Lane& L)
 {
     double xn[6], pn[6], Fn[6], s2[3];
     const double span = L.tmax - L.t;
     const double hs = fmin(L.h, span);
-    double err = dopri5_trial<K0, K1, K2>(S, L.x, L.p, L.F, hs, P.atol, P.rtol, xn, pn, Fn, s2);
+    double err = RK == 1
+                     ? dop853_trial<K0, K1, K2>(S, L.x, L.p, L.F, hs, P.atol, P.rtol, xn, pn, Fn, s2)
+                     : dopri5_trial<K0, K1, K2>(S, L.x, L.p, L.F, hs, P.atol, P.rtol, xn, pn, Fn, s2);
     if (P.fixed_step) err = 0.0;
     if (!(err <= 1.0e300)) err = INFINITY;   // NaN or inf: reject
     if (err <= 1.0) {
@@ -484,14 +597,14 @@ QD void lane_step(const Sys& S, const Prm& P, Lane& L)
         else if (m2 > L.rstop2) L.status = OK_RSTOP;
         else if (L.t >= L.tmax) L.status = OK_TMAX;
         if (!P.fixed_step) {
-            double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * ctrl_pow(err)));
+            double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * ctrl_pow<RK>(err)));
             if (L.last_rej && fac > 1.0) fac = 1.0;
             L.h = hs * fac;
         }
         L.last_rej = 0;
     } else {
         L.nrej += 1;
-        L.h = hs * fmax(0.2, 0.9 * ctrl_pow(err));
+        L.h = hs * fmax(0.2, 0.9 * ctrl_pow<RK>(err));
         L.last_rej = 1;
     }
     if (L.status == RUNNING && !P.fixed_step && L.h < 1e-12 * L.tmax) L.status = FAIL_HMIN;

@@ -1,8 +1,9 @@
 """Full-wave run of the propagation kernel for counting FP64 work per step.
 
-Every lane integrates the same number of fixed-size RK5(4) steps (no lane
-finishes early, no rejections), so hardware FP64 instruction counters divided
-by (lanes x steps) give the FP64 operations of one trial step.  Run under
+Every lane integrates the same number of fixed-size steps of the chosen RK
+variant (no lane finishes early, no rejections), so hardware FP64
+instruction counters divided by (lanes x steps) give the FP64 operations of
+one trial step.  Run under
 ``rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64
 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64``.
 """
@@ -24,6 +25,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=256 * 1024)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--h", type=float, default=0.25)
+    ap.add_argument("--rk", type=int, default=0, help="0: DOPRI5, 1: DOP853")
     args = ap.parse_args()
     import torch
 
@@ -31,7 +33,7 @@ def main():
     import paper_2304_02731_amd as Q
 
     wl = W.config_batched()
-    prm = dataclasses.replace(wl.params, fixed_step=1, h_fixed=args.h)
+    prm = dataclasses.replace(wl.params, fixed_step=1, h_fixed=args.h, rk=args.rk)
     ctx = Q.Context(wl.system, prm, device=0)
     ctx.set_instances(wl.instances)
     n = args.lanes
@@ -48,7 +50,7 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     ns = st.nstep.cpu()
-    print(json.dumps({"lanes": n, "steps_min": int(ns.min()), "steps_max": int(ns.max()),
+    print(json.dumps({"rk": args.rk, "lanes": n, "steps_min": int(ns.min()), "steps_max": int(ns.max()),
                       "lane_steps": int(ns.sum()), "kernel_ms": e0.elapsed_time(e1)}), flush=True)
 
 

@@ -24,6 +24,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "qcams.h")
 OK, EINVAL, EUNBOUND, ENOROOT, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
 MORSE, LJ, BUCK = 0, 1, 2
 B_FIXED, B_AREA, B_PROPOSAL = 0, 1, 2
+RK_DOPRI5, RK_DOP853 = 0, 1
 MLP_NPARAM, MLP_NIN, MLP_NOUT, PROP_CELLS = 34436, 6, 4, 8192
 RUNNING, OK_RSTOP, OK_TMAX, FAIL_MAXSTEPS, FAIL_NONFINITE, FAIL_HMIN, COLLAPSE = range(7)
 QUENCH, R1, R2, DISS, UNRESOLVED, FAILED = range(6)
@@ -55,7 +56,8 @@ class Params(C.Structure):
     _fields_ = [("R0", C.c_double), ("t_stop", C.c_double), ("r_stop", C.c_double),
                 ("atol", C.c_double), ("rtol", C.c_double), ("gb_sigma", C.c_double),
                 ("h_fixed", C.c_double), ("fixed_step", C.c_int32),
-                ("literal_bound", C.c_int32), ("max_steps", C.c_int64)]
+                ("literal_bound", C.c_int32), ("max_steps", C.c_int64), ("rk", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Instance(C.Structure):
@@ -71,10 +73,10 @@ class StateC(C.Structure):
 
 class RunOpts(C.Structure):
     _fields_ = [("blocks", C.c_int32), ("refill_min", C.c_int32), ("check_every", C.c_int32),
-                ("lpt", C.c_int32), ("graph", C.c_int32), ("pad", C.c_int32)]
+                ("lpt", C.c_int32), ("graph", C.c_int32), ("rk", C.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class OutcomeC(C.Structure):
@@ -116,8 +118,8 @@ def lib():
     L.qcams_run.argtypes = [vp, C.POINTER(RunOpts), C.POINTER(StateC), vp, C.POINTER(OutcomeC),
                             vp, vp, vp, vp]
     L.qcams_last_run_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
-    L.qcams_autotune.argtypes = [vp, C.POINTER(StateC), C.POINTER(OutcomeC), vp, vp, i32,
-                                 C.POINTER(RunOpts), C.POINTER(C.c_double)]
+    L.qcams_autotune.argtypes = [vp, C.POINTER(StateC), C.POINTER(OutcomeC), vp, vp, i32, i32,
+                                 C.c_double, C.POINTER(RunOpts), C.POINTER(C.c_double)]
     L.qcams_mlp_create.argtypes = [C.POINTER(vp), C.c_int, vp, C.c_uint64]
     L.qcams_mlp_destroy.argtypes = [vp]
     L.qcams_mlp_destroy.restype = None
@@ -177,7 +179,8 @@ def make_system(system, masses_me: Optional[Sequence[float]] = None) -> System:
 def make_params(p) -> Params:
     q = Params()
     for f, _ in Params._fields_:
-        setattr(q, f, getattr(p, f))
+        if f != "pad":
+            setattr(q, f, getattr(p, f, 0))
     return q
 
 
@@ -363,13 +366,15 @@ class Context:
         self._check(lib().qcams_last_run_kernel_ms(self._h, C.byref(ms)), "qcams_last_run_kernel_ms")
         return ms.value
 
-    def autotune(self, buf, reps: int = 1):
-        """Fastest qcams_run options on the installed instances (qcams_autotune)."""
+    def autotune(self, buf, reps: int = 1, search_rk: bool = False, energy_gate: float = 1e-8):
+        """Fastest qcams_run options on the installed instances (qcams_autotune);
+        with search_rk also the RK variant, among those keeping the energy gate."""
         best = RunOpts()
         ms = C.c_double()
         self._check(lib().qcams_autotune(self._h, C.byref(buf["state"].c()),
                                          C.byref(buf["outcome"].c()), buf["ids"].data_ptr(),
-                                         buf["xs"].data_ptr(), reps, C.byref(best), C.byref(ms)),
+                                         buf["xs"].data_ptr(), reps, int(search_rk),
+                                         float(energy_gate), C.byref(best), C.byref(ms)),
                     "qcams_autotune")
         return best, ms.value
 

@@ -33,6 +33,7 @@ RUNNING, OK_RSTOP, OK_TMAX, FAIL_MAXSTEPS, FAIL_NONFINITE, FAIL_HMIN, COLLAPSE =
 
 # impact-parameter modes
 B_FIXED, B_AREA, B_PROPOSAL = 0, 1, 2
+RK_DOPRI5, RK_DOP853 = 0, 1
 
 
 @dataclasses.dataclass(frozen=True)

@@ -130,11 +130,19 @@ def test_init_rejects_ids_outside_instances(Q, torch):
 
 # ----------------------------------------------------------------------------
 def _short_horizon(Q, torch, orc, wl, ids, periods, **prm):
+    """GPU and oracle integrate the same initial states over a few periods.
+    Where both take the same steps (equal accepted and rejected counts) the
+    states agree to 1e-9 relative.  An accept/reject decision taken at an
+    error estimate within rounding of 1 can part the two step sequences;
+    then both are valid integrations at the tolerances and each is compared
+    with a tight-tolerance DOP853 reference: the GPU's error may not exceed
+    three times the largest error of the oracle over the sample (+1e-9)."""
     ctx = _ctx(Q, wl, **prm)
     tid, st, smp = _gpu_init(Q, torch, ctx, ids)
     sys = orc.make_system(wl.system)
     p = dataclasses.replace(wl.params, **prm) if prm else wl.params
     oprm = orc.make_params(p)
+    tight = orc.make_params(dataclasses.replace(p, atol=1e-14, rtol=3e-14, rk=W.RK_DOP853))
     which = _inst_of(wl, ids)
     levs = {k: orc.level(sys, wl.instances[k].v, wl.instances[k].j) for k in set(which)}
     T = np.array([periods * levs[k][3] for k in which])
@@ -145,48 +153,77 @@ def _short_horizon(Q, torch, orc, wl, ids, periods, **prm):
     d = st.d.cpu().numpy()
     status = st.status.cpu().numpy()
     nstep = st.nstep.cpu().numpy()
-    worst = 0.0
+    nrej = st.nrej.cpu().numpy()
+    worst, parted = 0.0, []
     for c, (i, k) in enumerate(zip(ids, which)):
         I = wl.instances[k]
         y0, aux, _ = orc.init(sys, oprm, orc.make_instance(I), levs[k], int(i))
-        so, y, a, ns, nr = orc.propagate(sys, oprm, y0, np.r_[0.0, T[c], 1e9, aux[3], aux[4], 0])
+        box = np.r_[0.0, T[c], 1e9, aux[3], aux[4], 0]
+        so, y, a, ns, nr = orc.propagate(sys, oprm, y0, box)
         assert status[c] == so == Q.OK_TMAX
         assert d[Q.F_T, c] == a[0] == T[c]
         rel = np.abs(d[:12, c] - y) / np.maximum(np.abs(y), 1.0)
-        worst = max(worst, rel.max())
-        assert rel.max() < 1e-9, (i, rel.max(), nstep[c], ns)
+        if (nstep[c], nrej[c]) == (ns, nr):
+            worst = max(worst, rel.max())
+            assert rel.max() < 1e-9, (i, rel.max(), nstep[c], ns)
+        elif not p.fixed_step:
+            parted.append((c, i, y, rel.max(), (nstep[c], nrej[c], ns, nr)))
+        else:
+            raise AssertionError(("fixed-step counts differ", i, nstep[c], ns))
+    if parted:
+        e_orc, e_gpu = 0.0, []
+        for c, (i, k) in enumerate(zip(ids, which)):
+            I = wl.instances[k]
+            y0, aux, _ = orc.init(sys, oprm, orc.make_instance(I), levs[k], int(i))
+            box = np.r_[0.0, T[c], 1e9, aux[3], aux[4], 0]
+            _, yr, _, _, _ = orc.propagate(sys, tight, y0, box)
+            _, y, _, _, _ = orc.propagate(sys, oprm, y0, box)
+            scale = np.maximum(np.abs(yr), 1.0)
+            e_orc = max(e_orc, (np.abs(y - yr) / scale).max())
+            e_gpu.append((np.abs(d[:12, c] - yr) / scale).max())
+        for c, i, y, r, counts in parted:
+            assert e_gpu[c] <= 3 * e_orc + 1e-9, (i, e_gpu[c], e_orc, r, counts)
+        print("%d of %d step sequences parted; largest oracle error %.2e, GPU error on those %.2e"
+              % (len(parted), len(ids), e_orc, max(e_gpu[c] for c, *_ in parted)))
     return worst
 
 
-def test_short_horizon_states_match(Q, torch, orc):
+RK_VARIANTS = pytest.mark.parametrize("rk", [W.RK_DOPRI5, W.RK_DOP853], ids=["dopri5", "dop853"])
+
+
+@RK_VARIANTS
+def test_short_horizon_states_match(Q, torch, orc, rk):
     """Five vibrational periods from the initial state, adaptive steps."""
     wl = W.config_batched()
     rng = np.random.default_rng(7)
     ids = np.sort(rng.choice(wl.n_traj, 300, replace=False))
-    worst = _short_horizon(Q, torch, orc, wl, ids, 5.0)
+    worst = _short_horizon(Q, torch, orc, wl, ids, 5.0, rk=rk)
     print("short-horizon worst relative difference %.2e" % worst)
 
 
-def test_short_horizon_mixed_potentials(Q, torch, orc):
+@RK_VARIANTS
+def test_short_horizon_mixed_potentials(Q, torch, orc, rk):
     """LJ / Morse / Buckingham surface (the specialised kernel for that triple)."""
     wl = W.config_mixed(per_inst=3)
     rng = np.random.default_rng(8)
     ids = np.sort(rng.choice(wl.n_traj, 200, replace=False))
-    _short_horizon(Q, torch, orc, wl, ids, 3.0)
+    _short_horizon(Q, torch, orc, wl, ids, 3.0, rk=rk)
 
 
-def test_short_horizon_generic_kernel(Q, torch, orc):
+@RK_VARIANTS
+def test_short_horizon_generic_kernel(Q, torch, orc, rk):
     """A kind triple without a specialised kernel (run-time pair dispatch)."""
     s = W.h2ca_system()
     bc = W.Pair("buck", {"A": 50.0, "b": 1.5, "C6": 40.0})
     wl = W.config_batched(per_inst=2)
     wl.system = W.System(s.masses_amu, (s.pairs[0], bc, s.pairs[2]), "h2 generic")
-    _short_horizon(Q, torch, orc, wl, np.arange(0, 192, 3), 3.0)
+    _short_horizon(Q, torch, orc, wl, np.arange(0, 192, 3), 3.0, rk=rk)
 
 
-def test_fixed_step_mode_matches(Q, torch, orc):
+@RK_VARIANTS
+def test_fixed_step_mode_matches(Q, torch, orc, rk):
     wl = W.config_batched(per_inst=4)
-    _short_horizon(Q, torch, orc, wl, np.arange(0, 384, 5), 2.0, fixed_step=1, h_fixed=0.5)
+    _short_horizon(Q, torch, orc, wl, np.arange(0, 384, 5), 2.0, fixed_step=1, h_fixed=0.5, rk=rk)
 
 
 # ----------------------------------------------------------------------------
@@ -265,11 +302,12 @@ def test_classify_same_final_state(Q, torch, orc):
     assert np.allclose(xs[sel, Q.XS_WTOT], Wt[sel], rtol=1e-6, atol=1e-9)
 
 
-def test_cross_sections_statistical(Q, torch, orc):
+@RK_VARIANTS
+def test_cross_sections_statistical(Q, torch, orc, rk):
     """Independent full runs (GPU vs oracle, same seeds): per-channel cross
     sections agree within 3 combined standard errors."""
     inst = [W.Instance(5.0e4, 4, 0, 1200, 0, 4242, W.B_AREA, 0.0, 6.0)]
-    wl = W.Workload("stat", W.h2ca_system(), W.Params(), inst)
+    wl = W.Workload("stat", W.h2ca_system(), W.Params(rk=rk), inst)
     ctx = _ctx(Q, wl)
     tid = ctx.all_ids()
     n = tid.numel()

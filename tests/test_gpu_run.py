@@ -53,14 +53,15 @@ def _same(a, b):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
-def test_run_is_schedule_independent(Q, torch):
+@pytest.mark.parametrize("rk", [0, 2], ids=["context_dopri5", "dop853"])
+def test_run_is_schedule_independent(Q, torch, rk):
     wl = _mixed_energy_workload()
     ctx = Q.Context(wl.system, wl.params)
     ctx.set_instances(wl.instances)
     buf = ctx.new_run_buffers()
     ref = None
     for blocks, rm, ce, lpt in [(0, 1, 1, 1), (3, 1, 1, 1), (5, 64, 1, 0), (2, 8, 7, 1), (1, 1, 3, 0)]:
-        o = Q.RunOpts(blocks=blocks, refill_min=rm, check_every=ce, lpt=lpt, graph=0)
+        o = Q.RunOpts(blocks=blocks, refill_min=rm, check_every=ce, lpt=lpt, graph=0, rk=rk)
         ctx.run(buf, o)
         torch.cuda.synchronize()
         snap = _snapshot(buf)
@@ -131,20 +132,39 @@ def test_graph_replays_match_eager(Q, torch):
         _same(ref, _snapshot(buf))
 
 
-def test_autotune_returns_valid_options(Q, torch):
+@pytest.mark.parametrize("search_rk", [False, True], ids=["schedule", "schedule_and_variant"])
+def test_autotune_returns_valid_options(Q, torch, search_rk):
     wl = _mixed_energy_workload(per=32)
     ctx = Q.Context(wl.system, wl.params)
     ctx.set_instances(wl.instances)
     buf = ctx.new_run_buffers()
-    best, ms = ctx.autotune(buf, reps=1)
+    best, ms = ctx.autotune(buf, reps=1, search_rk=search_rk, energy_gate=1e-8)
     assert ms > 0 and best.blocks > 0 and 1 <= best.refill_min <= 64 and best.check_every >= 1
-    ctx.run(buf, Q.RunOpts(graph=0, refill_min=1, check_every=1, lpt=1))
+    assert best.rk in ((1, 2) if search_rk else (0,))
+    ctx.run(buf, Q.RunOpts(graph=0, refill_min=1, check_every=1, lpt=1, rk=best.rk))
     torch.cuda.synchronize()
     ref = _snapshot(buf)
     ctx.run(buf, best)
     torch.cuda.synchronize()
     _same(ref, _snapshot(buf))
+    ok = ref["label"] != Q.FAILED
+    assert np.all(np.abs(ref["od"][3][ok]) < 1e-8)
     print("autotuned", best.as_dict(), "%.2f ms" % ms)
+
+
+def test_variant_override_equals_context_variant(Q, torch):
+    """RunOpts.rk = 2 on a DOPRI5 context equals a DOP853 context's run."""
+    wl = _mixed_energy_workload(per=48)
+    out = []
+    for rk_ctx, rk_opt in [(W.RK_DOP853, 0), (W.RK_DOPRI5, 2)]:
+        p = W.Params(rk=rk_ctx)
+        ctx = Q.Context(wl.system, p)
+        ctx.set_instances(wl.instances)
+        buf = ctx.new_run_buffers()
+        ctx.run(buf, Q.RunOpts(graph=1, refill_min=1, check_every=8, lpt=1, rk=rk_opt))
+        torch.cuda.synchronize()
+        out.append(_snapshot(buf))
+    _same(out[0], out[1])
 
 
 def test_run_cross_sections_vs_oracle(Q, torch, orc):
