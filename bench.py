@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--refill-min", type=int, default=1)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-lpt", action="store_true")
+    ap.add_argument("--lanes", type=int, default=4, choices=[1, 4],
+                    help="lanes per trajectory in the persistent kernel")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--learned", action="store_true",
                     help="also train the proposal network and report variance x GPU-seconds, "
@@ -107,7 +109,7 @@ def main():
     stream = torch.cuda.Stream()
     opts = Q.RunOpts(blocks=args.blocks, refill_min=args.refill_min,
                      check_every=args.check_every, lpt=0 if args.no_lpt else 1,
-                     graph=0 if args.no_graph else 1)
+                     graph=0 if args.no_graph else 1, lanes=args.lanes)
     tuned = None
     with torch.cuda.stream(stream):
         buf = ctx.new_run_buffers()
@@ -190,8 +192,8 @@ def main():
                      "unit": "TFLOP/s",
                      "frac": achieved * 1e12 / PEAK_FP64_VECTOR if achieved else None,
                      "traffic": None,
-                     "kernel": ("k_persistent<0,0,0,%d>" if args.path == "run"
-                                else "k_propagate<0,0,0,%d>") % rk,
+                     "kernel": ("k_persistent<%d,0,0,0,%d>" % (args.lanes, rk)
+                                if args.path == "run" else "k_propagate<0,0,0,%d>" % rk),
                      "timed_ms": prop_ms, "trial_steps": trial_steps,
                      "flop_per_trial_step": f_step},
         "path": args.path, "run_opts": opts.as_dict(), "autotune": tuned,

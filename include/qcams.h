@@ -204,9 +204,10 @@ int qcams_set_instances(qcams_ctx *ctx, const qcams_instance *inst, int32_t n_in
 int qcams_init_conditions(qcams_ctx *ctx, const int64_t *ids, int64_t n,
                           const qcams_state *st, double *sample, void *stream);
 
-/* Integrate trajectories 0..n-1 of st with the adaptive RK5(4) (Eq. (3)-(4))
- * until each stops (status != RUNNING).  Trajectories already stopped are
- * left untouched.  async. */
+/* Integrate trajectories 0..n-1 of st with the adaptive RK integrator of
+ * the context's variant (Eq. (3)-(4)) until each stops (status != RUNNING),
+ * one lane per trajectory.  Trajectories already stopped are left
+ * untouched.  async. */
 int qcams_propagate(qcams_ctx *ctx, const qcams_state *st, int64_t n, void *stream);
 
 /* Product analysis (Sec. 2.2, Eq. (8)-(11)) of the final states 0..n-1.
@@ -227,23 +228,30 @@ int qcams_cross_sections(qcams_ctx *ctx, const qcams_outcome *out, const int64_t
 /* Options of the fused persistent run. */
 typedef struct {
     int32_t blocks;      /* persistent grid in 256-thread workgroups; 0 = 1 per compute unit */
-    int32_t refill_min;  /* refill a wave once this many of its 64 lanes are idle (1..64; 0 = 1) */
+    int32_t refill_min;  /* refill a wave once this many of its slots are idle (0 = 1) */
     int32_t check_every; /* trial steps between refill checks (0 = 1) */
     int32_t lpt;         /* 1: start instances longest-expected-first (cost ~ 1/(v_c tau_vj)) */
     int32_t graph;       /* 1: capture the launch sequence once per buffer set and replay it */
     int32_t rk;          /* 0: the context's variant; 1: DOPRI5; 2: DOP853 */
+    int32_t lanes;       /* lanes per trajectory: 1, or 4 (a quad shares the arithmetic of one
+                            trajectory; 16 slots per wave); 0 = 4.  Both give bit-identical
+                            trajectories; 4 cuts the latency of each step to about 40 % */
+    int32_t pad;
 } qcams_run_opts;
 
 /* The whole hot path over every installed trajectory (N = sum of n_traj):
- * initial conditions, propagation in one persistent launch whose lanes take
- * a new trajectory as soon as theirs stops, classification, and the
+ * initial conditions, propagation in one persistent launch whose slots (a
+ * lane or a quad of lanes) take a new trajectory as soon as theirs stops,
+ * classification, and the
  * per-instance reduction of qcams_cross_sections.  Results are stored at
  * each trajectory's natural position p (instances in id order, ids
  * consecutive inside an instance): st, sample (may be NULL), out, and
  * ids[p] (device int64 [N], written) as the matching trajectory id.  xs,
  * hist (may be NULL) as in qcams_cross_sections.  opts may be NULL
  * (defaults: 1 workgroup per CU, refill_min 1, check_every 8, LPT, no
- * graph).  With opts->graph the small set-up and analysis launches around
+ * graph, the context's RK variant, 4 lanes per trajectory).  Per-trajectory
+ * results do not depend on blocks, refill_min, check_every, lpt, graph or
+ * lanes.  With opts->graph the small set-up and analysis launches around
  * the persistent kernel are captured into two HIP graphs on first use (per
  * buffer set, order option and instance count) and replayed afterwards; the
  * persistent kernel is launched between them.  async.  Errors: EINVAL,
@@ -257,18 +265,20 @@ int qcams_run(qcams_ctx *ctx, const qcams_run_opts *opts, const qcams_state *st,
  * run to finish.  sync.  Errors: EINVAL (no run yet), EHIP. */
 int qcams_last_run_kernel_ms(qcams_ctx *ctx, double *ms);
 
-/* Time qcams_run over a grid of options (grid 1/2/4 workgroups per CU,
- * refill_min 1/8/32, check_every 1/8, instance order LPT / natural) on the
- * installed instances -- install a calibration subset first -- and return
- * the fastest in *best (graph off) with its time in *best_ms (may be NULL).
- * Buffers as for qcams_run; each option is run `reps` times and the minimum
- * kept.  With search_rk = 1 the RK variant is chosen first: DOPRI5 and
- * DOP853 are each run with the default schedule and the faster of those
- * whose largest |H(t_f) - H(0)| / escale over non-failed trajectories is
- * below energy_gate (<= 0: no gate) is kept (best->rk = 1 or 2); the
- * variant changes per-trajectory results, the schedule does not.  With
- * search_rk = 0 the context's variant is used (best->rk = 0).  sync.
- * Errors as qcams_run; EINVAL also when no variant keeps the gate. */
+/* Choose fast qcams_run options on the installed instances -- install a
+ * calibration subset first -- by timing runs: coordinate descent, two
+ * sweeps from the defaults, over lanes per trajectory (4, 1), grid (1-4
+ * workgroups per CU), refill_min (1, 4, 16), check_every (1, 4, 8) and
+ * instance order (LPT, natural).  Returns the fastest in *best (graph off)
+ * with its time in *best_ms (may be NULL).  Buffers as for qcams_run; each
+ * option is run `reps` times and the minimum kept.  With search_rk = 1 the
+ * RK variant is chosen first: DOPRI5 and DOP853 are each run with the
+ * default schedule and the faster of those whose largest |H(t_f) - H(0)| /
+ * escale over non-failed trajectories is below energy_gate (<= 0: no gate)
+ * is kept (best->rk = 1 or 2); the variant changes per-trajectory results,
+ * the schedule does not.  With search_rk = 0 the context's variant is used
+ * (best->rk = 0).  sync.  Errors as qcams_run; EINVAL also when no variant
+ * keeps the gate. */
 int qcams_autotune(qcams_ctx *ctx, const qcams_state *st, const qcams_outcome *out, int64_t *ids,
                    double *xs, int32_t reps, int32_t search_rk, double energy_gate,
                    qcams_run_opts *best, double *best_ms);

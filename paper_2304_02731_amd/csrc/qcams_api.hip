@@ -242,14 +242,60 @@ __global__ void k_run_tables(const Inst* inst, int n_inst, const int32_t* ord_in
     ids[pos] = inst[k].first_id + local;
 }
 
-template <int K0, int K1, int K2, int RK>
+// A trajectory's slot is one lane (W = 1) or a quad of lanes (W = 4, see the
+// lane layouts of the device header); the idle-slot count and a slot's rank
+// among the idle slots are the lane counts divided by W.
+template <int W>
+__device__ inline void load_traj(const double* d, int64_t ld, int64_t pos, int c, LaneW<W>& L)
+{
+    if constexpr (W == 1) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            L.x[f] = d[f * ld + pos];
+            L.p[f] = d[(6 + f) * ld + pos];
+        }
+    } else {
+        if (c < 3) {
+            L.x[0] = d[c * ld + pos];
+            L.x[1] = d[(3 + c) * ld + pos];
+            L.p[0] = d[(6 + c) * ld + pos];
+            L.p[1] = d[(9 + c) * ld + pos];
+        } else {
+            L.x[0] = L.x[1] = L.p[0] = L.p[1] = 0.0;
+        }
+    }
+}
+
+template <int W>
+__device__ inline void store_traj(double* d, int64_t ld, int64_t pos, int c, const LaneW<W>& L)
+{
+    if constexpr (W == 1) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            d[f * ld + pos] = L.x[f];
+            d[(6 + f) * ld + pos] = L.p[f];
+        }
+    } else {
+        if (c < 3) {
+            d[c * ld + pos] = L.x[0];
+            d[(3 + c) * ld + pos] = L.x[1];
+            d[(6 + c) * ld + pos] = L.p[0];
+            d[(9 + c) * ld + pos] = L.p[1];
+        }
+    }
+}
+
+template <int W, int K0, int K1, int K2, int RK>
 __global__ void __launch_bounds__(256)
 k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min, int check_every,
              double* d, int32_t* nstep, int32_t* nrej, uint8_t* status, int64_t ld)
 {
+    constexpr int SLOTS = 64 / W;
     const unsigned lane = __lane_id();
+    const int c = W == 1 ? 0 : (int)(lane & 3u);
+    const Role R = make_role(S, c);
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    Lane L;
+    LaneW<W> L;
     int64_t pos = -1;
     bool active = false;
     bool exhausted = false;
@@ -257,8 +303,8 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
     for (;;) {
         // ---- refill (wave-uniform) ----
         const unsigned long long idle = __ballot(!active);
-        const int nidle = __popcll(idle);
-        const bool none_active = nidle == 64;
+        const int nidle = __popcll(idle) / W;
+        const bool none_active = nidle == SLOTS;
         if (!exhausted && (nidle >= refill_min || (none_active && nidle > 0))) {
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(counter, (unsigned long long)nidle);
@@ -267,14 +313,10 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
             base = ((unsigned long long)hi32 << 32) | lo32;
             if (base + (unsigned long long)nidle >= (unsigned long long)M.N) exhausted = true;
             if (!active) {
-                const int64_t w = (int64_t)base + __popcll(idle & lt_mask);
+                const int64_t w = (int64_t)base + __popcll(idle & lt_mask) / W;
                 if (w < M.N) {
                     pos = M.order[w];
-#pragma unroll
-                    for (int f = 0; f < 6; ++f) {
-                        L.x[f] = d[f * ld + pos];
-                        L.p[f] = d[(6 + f) * ld + pos];
-                    }
+                    load_traj<W>(d, ld, pos, c, L);
                     L.t = d[QCAMS_F_T * ld + pos];
                     L.tmax = d[QCAMS_F_TMAX * ld + pos];
                     const double rs = d[QCAMS_F_RSTOP * ld + pos];
@@ -286,7 +328,7 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
                     L.status = status[pos];
                     if (L.status == RUNNING) {
                         double s2[3];
-                        force<K0, K1, K2>(S, L.x, L.F, s2);
+                        force_w<W, K0, K1, K2>(S, R, L.x, L.F, s2);
                         if (!is_finite(L.t) || !is_finite(L.tmax) || !is_finite(L.h)) L.status = FAIL_NONFINITE;
                         else if (L.t >= L.tmax) L.status = OK_TMAX;
                         else if (L.nstep >= P.max_steps) L.status = FAIL_MAXSTEPS;
@@ -298,20 +340,18 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
         if (__ballot(active) == 0ull) break;
         // ---- integrate ----
         for (int s = 0; s < check_every; ++s) {
-            if (active && L.status == RUNNING) lane_step<K0, K1, K2, RK>(S, P, L);
+            if (active && L.status == RUNNING) lane_step_w<W, K0, K1, K2, RK>(S, R, P, L);
         }
-        // ---- retire finished lanes ----
+        // ---- retire finished trajectories ----
         if (active && L.status != RUNNING) {
-#pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                d[f * ld + pos] = L.x[f];
-                d[(6 + f) * ld + pos] = L.p[f];
+            store_traj<W>(d, ld, pos, c, L);
+            if (c == 0) {
+                d[QCAMS_F_T * ld + pos] = L.t;
+                d[QCAMS_F_H * ld + pos] = L.h;
+                nstep[pos] = L.nstep;
+                nrej[pos] = L.nrej;
+                status[pos] = (uint8_t)L.status;
             }
-            d[QCAMS_F_T * ld + pos] = L.t;
-            d[QCAMS_F_H * ld + pos] = L.h;
-            nstep[pos] = L.nstep;
-            nrej[pos] = L.nrej;
-            status[pos] = (uint8_t)L.status;
             active = false;
             L.status = RUNNING;
         }
@@ -607,15 +647,20 @@ struct PropagateL {
 
 template <int K0, int K1, int K2, int RK>
 struct PersistentL {
-    static void go(qcams_ctx* c, int blocks, int refill_min, int check_every, const int64_t* order,
-                   const qcams_state* st, hipStream_t s)
+    static void go(qcams_ctx* c, int width, int blocks, int refill_min, int check_every,
+                   const int64_t* order, const qcams_state* st, hipStream_t s)
     {
         RunMap M{order, c->n_total};
         Prm P = c->prm;
         P.rk = RK;
-        hipLaunchKernelGGL((k_persistent<K0, K1, K2, RK>), dim3(blocks), dim3(256), 0, s, c->sys, P,
-                           M, c->d_counter, refill_min, check_every, st->d, st->nstep, st->nrej,
-                           st->status, st->ld);
+        if (width == 4)
+            hipLaunchKernelGGL((k_persistent<4, K0, K1, K2, RK>), dim3(blocks), dim3(256), 0, s,
+                               c->sys, P, M, c->d_counter, refill_min, check_every, st->d,
+                               st->nstep, st->nrej, st->status, st->ld);
+        else
+            hipLaunchKernelGGL((k_persistent<1, K0, K1, K2, RK>), dim3(blocks), dim3(256), 0, s,
+                               c->sys, P, M, c->d_counter, refill_min, check_every, st->d,
+                               st->nstep, st->nrej, st->status, st->ld);
     }
 };
 
@@ -965,6 +1010,12 @@ static int run_variant(const qcams_ctx* c, const qcams_run_opts* o)
     return o->rk == 1 ? 0 : (o->rk == 2 ? 1 : c->prm.rk);
 }
 
+// lanes per trajectory of the persistent kernel (default: a quad)
+static int run_width(const qcams_run_opts* o)
+{
+    return o->lanes == 1 ? 1 : 4;
+}
+
 // The run is three launch groups: the small set-up kernels (work order,
 // initial conditions, counter reset), the persistent propagation kernel, and
 // the small analysis kernels (classification, reduction).  In graph mode the
@@ -986,10 +1037,12 @@ static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const qcams
                               hipStream_t s)
 {
     const int blocks = o->blocks > 0 ? o->blocks : c->n_cu;
-    const int rm = o->refill_min < 1 ? 1 : (o->refill_min > 64 ? 64 : o->refill_min);
+    const int slots = 64 / run_width(o);
+    const int rm = o->refill_min < 1 ? 1 : (o->refill_min > slots ? slots : o->refill_min);
     const int ce = o->check_every < 1 ? 1 : o->check_every;
     if (hipEventRecord(c->ev_prop[0], s) != hipSuccess) return QCAMS_EHIP;
-    with_variant<PersistentL>(c, run_variant(c, o), c, blocks, rm, ce, (const int64_t*)c->d_order, st, s);
+    with_variant<PersistentL>(c, run_variant(c, o), c, run_width(o), blocks, rm, ce,
+                              (const int64_t*)c->d_order, st, s);
     if (hipEventRecord(c->ev_prop[1], s) != hipSuccess) return QCAMS_EHIP;
     return hipGetLastError() == hipSuccess ? QCAMS_OK : QCAMS_EHIP;
 }
@@ -1037,7 +1090,8 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
     o.lpt = 1;
     o.graph = 0;
     if (opts) o = *opts;
-    if (o.blocks < 0 || o.refill_min < 0 || o.check_every < 0 || o.rk < 0 || o.rk > 2)
+    if (o.blocks < 0 || o.refill_min < 0 || o.check_every < 0 || o.rk < 0 || o.rk > 2 ||
+        (o.lanes != 0 && o.lanes != 1 && o.lanes != 4))
         return fail(c, QCAMS_EINVAL, "invalid run option");
     for (const Inst& I : c->h_inst)
         if (I.b_mode == 2 && (!sample || !c->d_prop_q))
@@ -1187,27 +1241,44 @@ int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out
         }
         if (rc == QCAMS_OK && !any) rc = QCAMS_EINVAL;
     }
-    const int blocks_c[3] = {c->n_cu, 2 * c->n_cu, 4 * c->n_cu};
-    const int refill_c[3] = {1, 8, 32};
-    const int check_c[2] = {1, 8};
-    for (int lpt = 1; lpt >= 0 && rc == QCAMS_OK; --lpt)
-        for (int bi = 0; bi < 3 && rc == QCAMS_OK; ++bi)
-            for (int ri = 0; ri < 3 && rc == QCAMS_OK; ++ri)
-                for (int ci = 0; ci < 2 && rc == QCAMS_OK; ++ci) {
-                    qcams_run_opts o{};
-                    o.blocks = blocks_c[bi];
-                    o.refill_min = refill_c[ri];
-                    o.check_every = check_c[ci];
-                    o.lpt = lpt;
-                    o.graph = 0;
-                    o.rk = rk;
-                    double tmin = 1e300;
-                    rc = tune_time(c, &o, st, out, ids, xs, reps, s, e0, e1, &tmin);
-                    if (rc == QCAMS_OK && tmin < best_t) {
-                        best_t = tmin;
-                        bo = o;
-                    }
+    // coordinate descent over the schedule options, two sweeps, from the
+    // defaults: lanes per trajectory, grid, refill threshold, check interval,
+    // instance order
+    qcams_run_opts cur{};
+    cur.blocks = c->n_cu;
+    cur.refill_min = 1;
+    cur.check_every = 8;
+    cur.lpt = 1;
+    cur.graph = 0;
+    cur.rk = rk;
+    cur.lanes = 4;
+    if (rc == QCAMS_OK) rc = tune_time(c, &cur, st, out, ids, xs, reps, s, e0, e1, &best_t);
+    bo = cur;
+    const int nb = 4, nr = 3, nc = 3;
+    const int blocks_c[nb] = {c->n_cu, 2 * c->n_cu, 3 * c->n_cu, 4 * c->n_cu};
+    const int refill_c[nr] = {1, 4, 16};
+    const int check_c[nc] = {1, 4, 8};
+    for (int sweep = 0; sweep < 2 && rc == QCAMS_OK; ++sweep)
+        for (int dim = 0; dim < 5 && rc == QCAMS_OK; ++dim) {
+            const int nv = dim == 0 ? 2 : dim == 1 ? nb : dim == 2 ? nr : dim == 3 ? nc : 2;
+            for (int v = 0; v < nv && rc == QCAMS_OK; ++v) {
+                qcams_run_opts o = bo;
+                if (dim == 0) o.lanes = v == 0 ? 4 : 1;
+                else if (dim == 1) o.blocks = blocks_c[v];
+                else if (dim == 2) o.refill_min = refill_c[v];
+                else if (dim == 3) o.check_every = check_c[v];
+                else o.lpt = 1 - v;
+                if (o.lanes == bo.lanes && o.blocks == bo.blocks && o.refill_min == bo.refill_min &&
+                    o.check_every == bo.check_every && o.lpt == bo.lpt)
+                    continue;
+                double tmin = 1e300;
+                rc = tune_time(c, &o, st, out, ids, xs, reps, s, e0, e1, &tmin);
+                if (rc == QCAMS_OK && tmin < best_t) {
+                    best_t = tmin;
+                    bo = o;
                 }
+            }
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(s);

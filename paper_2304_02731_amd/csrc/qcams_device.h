@@ -230,44 +230,144 @@ QD double dV_over_r(const Pot& P, double r, double ir)
 }
 
 // ---------------------------------------------------------------------------
+// Lane layouts of one trajectory.
+//
+// W = 1: one lane holds a whole trajectory; component arrays have six
+//   entries, (rho1 x, y, z, rho2 x, y, z).
+// W = 4: four consecutive lanes (a quad) share one trajectory.  Lane c < 3
+//   holds spatial component c -- entries (rho1_c, rho2_c) -- and evaluates
+//   pair c (AB, BC, CA) of the potential; lane 3 holds zeros and evaluates a
+//   copy of pair 0 that nobody reads.  Sums over the three spatial
+//   components (squared pair distances, error norms) are taken in one tree,
+//   (s_0 + s_1) + s_2, in both layouts (the quad adds s_3 = +0 to s_2, which
+//   is exact for the non-negative terms summed here); every other operation
+//   acts on one component with the same expression.  The layouts therefore
+//   give bit-identical trajectories (with contraction limited to single
+//   expressions, -ffp-contract=on).  W = 4 cuts the instructions a lane
+//   issues per step to about 40 %, for the long trajectories whose latency
+//   bounds a run.
+// ---------------------------------------------------------------------------
+template <int W> struct Lay;
+template <> struct Lay<1> { static constexpr int NC = 3; };
+template <> struct Lay<4> { static constexpr int NC = 1; };
+
+// A lane's part in its quad (W = 4 only).
+struct Role {
+    int c;     // spatial component and pair, 0..3
+    Pot pot;   // pair c's potential (pair 0 for c = 3)
+};
+
+QD Role make_role(const Sys& S, int c)
+{
+    Role R;
+    R.c = c;
+    const Pot& a = S.pot[0];
+    const Pot& b = S.pot[1];
+    const Pot& e = S.pot[2];
+    R.pot.kind = c == 1 ? b.kind : (c == 2 ? e.kind : a.kind);
+    R.pot.n = c == 1 ? b.n : (c == 2 ? e.n : a.n);
+    R.pot.m = c == 1 ? b.m : (c == 2 ? e.m : a.m);
+    R.pot.pad = 0;
+    R.pot.p0 = c == 1 ? b.p0 : (c == 2 ? e.p0 : a.p0);
+    R.pot.p1 = c == 1 ? b.p1 : (c == 2 ? e.p1 : a.p1);
+    R.pot.p2 = c == 1 ? b.p2 : (c == 2 ? e.p2 : a.p2);
+    return R;
+}
+
+// Exchange inside a quad (DPP quad permutations; every lane of the quad
+// active).  XOR1 swaps lanes (0,1),(2,3); XOR2 swaps (0,2),(1,3); BC<k>
+// broadcasts lane k.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E;
+template <int K> struct Bc { static constexpr int ctrl = K * 0x55; };
+
+template <int CTRL>
+__device__ inline double quad_perm(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ inline int quad_and(int v)
+{
+    v &= __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false);
+    return v & __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, false);
+}
+
+// (s_0 + s_1) + (s_2 + s_3) over the quad, the same value in all four lanes
+__device__ inline double quad_sum(double v)
+{
+    const double u = v + quad_perm<kDppXor1>(v);
+    return u + quad_perm<kDppXor2>(u);
+}
+
+// ---------------------------------------------------------------------------
 // Hamilton's equations (Eq. (3)-(4)) in separable form.
 // x = (rho1, rho2), p = (P1, P2).  dx/dt = p / mu is linear, so only the
 // force F(x) = -dV/dx is evaluated.  READING of the Jacobi signs (not fixed by
 // the paper): rho1 = r_B - r_A, rho2 = r_C - R_cm(AB); pair vectors
 // r_AB = rho1, r_BC = rho2 - cA rho1, r_CA = -rho2 - cB rho1.
-// Outputs the squared pair distances (for the stop rules) as a by-product.
+// Outputs the squared pair distances (for the stop rules) as a by-product;
+// in the quad layout every lane gets all three.
 // ---------------------------------------------------------------------------
-template <int K0, int K1, int K2>
-QD void force(const Sys& S, const double* x, double* F, double* s2)
+template <int W, int K0, int K1, int K2>
+QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double* s2)
 {
-    double rab[3], rbc[3], rca[3];
+    constexpr int NC = Lay<W>::NC;
+    double rab[NC], rbc[NC], rca[NC], qab[NC], qbc[NC], qca[NC];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < NC; ++a) {
         rab[a] = x[a];
-        rbc[a] = x[3 + a] - S.cA * x[a];
-        rca[a] = -x[3 + a] - S.cB * x[a];
+        rbc[a] = fma(-S.cA, x[a], x[NC + a]);
+        rca[a] = fma(-S.cB, x[a], -x[NC + a]);
+        qab[a] = rab[a] * rab[a];
+        qbc[a] = rbc[a] * rbc[a];
+        qca[a] = rca[a] * rca[a];
     }
-    const double sab = rab[0] * rab[0] + rab[1] * rab[1] + rab[2] * rab[2];
-    const double sbc = rbc[0] * rbc[0] + rbc[1] * rbc[1] + rbc[2] * rbc[2];
-    const double sca = rca[0] * rca[0] + rca[1] * rca[1] + rca[2] * rca[2];
-    double dab, dbc, dca, iab, ibc, ica;
-    sqrt_rsqrt(sab, dab, iab);
-    sqrt_rsqrt(sbc, dbc, ibc);
-    sqrt_rsqrt(sca, dca, ica);
-    const double gab = dV_over_r<K0>(S.pot[0], dab, iab);
-    const double gbc = dV_over_r<K1>(S.pot[1], dbc, ibc);
-    const double gca = dV_over_r<K2>(S.pot[2], dca, ica);
+    double sab, sbc, sca, gab, gbc, gca;
+    if constexpr (W == 1) {
+        sab = (qab[0] + qab[1]) + qab[2];
+        sbc = (qbc[0] + qbc[1]) + qbc[2];
+        sca = (qca[0] + qca[1]) + qca[2];
+        double dab, dbc, dca, iab, ibc, ica;
+        sqrt_rsqrt(sab, dab, iab);
+        sqrt_rsqrt(sbc, dbc, ibc);
+        sqrt_rsqrt(sca, dca, ica);
+        gab = dV_over_r<K0>(S.pot[0], dab, iab);
+        gbc = dV_over_r<K1>(S.pot[1], dbc, ibc);
+        gca = dV_over_r<K2>(S.pot[2], dca, ica);
+    } else {
+        sab = quad_sum(qab[0]);
+        sbc = quad_sum(qbc[0]);
+        sca = quad_sum(qca[0]);
+        const double s = R.c == 1 ? sbc : (R.c == 2 ? sca : sab);
+        double d, id;
+        sqrt_rsqrt(s, d, id);
+        // one kind for all pairs: specialised; otherwise the lane's own kind
+        constexpr int KU = (K0 >= 0 && K0 == K1 && K1 == K2) ? K0 : -1;
+        const double g = dV_over_r<KU>(R.pot, d, id);
+        gab = quad_perm<Bc<0>::ctrl>(g);
+        gbc = quad_perm<Bc<1>::ctrl>(g);
+        gca = quad_perm<Bc<2>::ctrl>(g);
+    }
     const double cgbc = S.cA * gbc, cgca = S.cB * gca;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < NC; ++a) {
         // -dV/drho1 = -g_AB r_AB + cA g_BC r_BC + cB g_CA r_CA
         F[a] = fma(cgca, rca[a], fma(cgbc, rbc[a], -gab * rab[a]));
         // -dV/drho2 = -g_BC r_BC + g_CA r_CA
-        F[3 + a] = fma(gca, rca[a], -gbc * rbc[a]);
+        F[NC + a] = fma(gca, rca[a], -gbc * rbc[a]);
     }
     s2[0] = sab;
     s2[1] = sbc;
     s2[2] = sca;
+}
+
+template <int K0, int K1, int K2>
+QD void force(const Sys& S, const double* x, double* F, double* s2)
+{
+    force_w<1, K0, K1, K2>(S, Role{}, x, F, s2);
 }
 
 QD double hamiltonian(const Sys& S, const double* x, const double* p)
@@ -342,49 +442,62 @@ constexpr double z5 = e6 * a65 + e7 * b5;
 constexpr double z6 = e7 * b6;
 }  // namespace dp
 
+// Sum over the spatial components c of per-component partial sums, in the
+// tree shared by both layouts (lane 3 of a quad contributes +0).
+template <int W>
+QD double comp_sum(const Role& R, const double* part)
+{
+    if constexpr (W == 1) {
+        return (part[0] + part[1]) + part[2];
+    } else {
+        return quad_sum(R.c < 3 ? part[0] : 0.0);
+    }
+}
+
 // One trial step.  In: x, p, F1 = F(x), h.  Out: xn, pn, F7 = F(xn), the
 // squared pair distances at xn, and the RMS error norm of Hairer-Norsett-
 // Wanner (I, Sec. II.4) over the 12 components, scaled by
 // atol + rtol max(|y|, |y'|).
-template <int K0, int K1, int K2>
-QD double dopri5_trial(const Sys& S, const double* x, const double* p, const double* F1,
-                       double h, double atol, double rtol, double* xn, double* pn,
-                       double* F7, double* s2)
+template <int W, int K0, int K1, int K2>
+QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const double* p,
+                       const double* F1, double h, double atol, double rtol, double* xn,
+                       double* pn, double* F7, double* s2)
 {
     using namespace dp;
-    double X[6], F2[6], F3[6], F4[6], F5[6], F6[6], junk[3];
+    constexpr int NC = Lay<W>::NC, N = 2 * NC;
+    double X[N], F2[N], F3[N], F4[N], F5[N], F6[N], junk[3];
     const double hh = h * h;
     // per-component 1/mu (uniform) and h^2/mu
     const double im0 = S.inv_mu12, im1 = S.inv_mu123;
     const double g0 = hh * im0, g1 = hh * im1;
-#define IM(i) ((i) < 3 ? im0 : im1)
-#define GG(i) ((i) < 3 ? g0 : g1)
+#define IM(i) ((i) < NC ? im0 : im1)
+#define GG(i) ((i) < NC ? g0 : g1)
 #pragma unroll
-    for (int i = 0; i < 6; ++i) X[i] = fma(h * c2 * IM(i), p[i], x[i]);
-    force<K0, K1, K2>(S, X, F2, junk);
+    for (int i = 0; i < N; ++i) X[i] = fma(h * c2 * IM(i), p[i], x[i]);
+    force_w<W, K0, K1, K2>(S, R, X, F2, junk);
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < N; ++i)
         X[i] = fma(GG(i), q31 * F1[i], fma(h * c3 * IM(i), p[i], x[i]));
-    force<K0, K1, K2>(S, X, F3, junk);
+    force_w<W, K0, K1, K2>(S, R, X, F3, junk);
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < N; ++i)
         X[i] = fma(GG(i), fma(q42, F2[i], q41 * F1[i]), fma(h * c4 * IM(i), p[i], x[i]));
-    force<K0, K1, K2>(S, X, F4, junk);
+    force_w<W, K0, K1, K2>(S, R, X, F4, junk);
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < N; ++i)
         X[i] = fma(GG(i), fma(q53, F3[i], fma(q52, F2[i], q51 * F1[i])),
                    fma(h * c5 * IM(i), p[i], x[i]));
-    force<K0, K1, K2>(S, X, F5, junk);
+    force_w<W, K0, K1, K2>(S, R, X, F5, junk);
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < N; ++i)
         X[i] = fma(GG(i), fma(q64, F4[i], fma(q63, F3[i], fma(q62, F2[i], q61 * F1[i]))),
                    fma(h * IM(i), p[i], x[i]));
-    force<K0, K1, K2>(S, X, F6, junk);
+    force_w<W, K0, K1, K2>(S, R, X, F6, junk);
     // step and error estimate (all but the F7 term) before the last force,
     // so that F2..F6 are dead when F7 is evaluated
-    double ep[6], ex[6];
+    double ep[N], ex[N];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < N; ++i) {
         xn[i] = fma(GG(i), fma(w5, F5[i], fma(w4, F4[i], fma(w3, F3[i], fma(w2, F2[i], w1 * F1[i])))),
                     fma(h * IM(i), p[i], x[i]));
         pn[i] = fma(h, fma(b6, F6[i], fma(b5, F5[i], fma(b4, F4[i], fma(b3, F3[i], b1 * F1[i])))),
@@ -395,17 +508,23 @@ QD double dopri5_trial(const Sys& S, const double* x, const double* p, const dou
     }
 #undef IM
 #undef GG
-    force<K0, K1, K2>(S, xn, F7, s2);
-    double acc = 0.0;
+    force_w<W, K0, K1, K2>(S, R, xn, F7, s2);
+    double part[NC];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        const double epi = h * fma(e7, F7[i], ep[i]);
-        const double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
-        const double sp = fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol);
-        const double qx = ex[i] * rcp_nr(sx), qp = epi * rcp_nr(sp);
-        acc = fma(qx, qx, fma(qp, qp, acc));
+    for (int c = 0; c < NC; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = c + k * NC;
+            const double epi = h * fma(e7, F7[i], ep[i]);
+            const double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
+            const double sp = fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol);
+            const double qx = ex[i] * rcp_nr(sx), qp = epi * rcp_nr(sp);
+            acc = fma(qx, qx, fma(qp, qp, acc));
+        }
+        part[c] = acc;
     }
-    return sqrt(acc * (1.0 / 12.0));
+    return sqrt(comp_sum<W>(R, part) * (1.0 / 12.0));
 }
 
 // ---------------------------------------------------------------------------
@@ -449,36 +568,37 @@ constexpr Derived derive()
 constexpr Derived T = derive();
 }  // namespace d8
 
-template <int K0, int K1, int K2>
-QD double dop853_trial(const Sys& S, const double* x, const double* p, const double* F1,
-                       double h, double atol, double rtol, double* xn, double* pn,
-                       double* F13, double* s2)
+template <int W, int K0, int K1, int K2>
+QD double dop853_trial(const Sys& S, const Role& R, const double* x, const double* p,
+                       const double* F1, double h, double atol, double rtol, double* xn,
+                       double* pn, double* F13, double* s2)
 {
     using namespace d8;
-    double F[NS][6], junk[3];
+    constexpr int NC = Lay<W>::NC, N = 2 * NC;
+    double F[NS][N], junk[3];
     const double hh = h * h;
     const double im0 = S.inv_mu12, im1 = S.inv_mu123;
     const double g0 = hh * im0, g1 = hh * im1;
-#define IM(i) ((i) < 3 ? im0 : im1)
-#define GG(i) ((i) < 3 ? g0 : g1)
+#define IM(i) ((i) < NC ? im0 : im1)
+#define GG(i) ((i) < NC ? g0 : g1)
 #pragma unroll
-    for (int i = 0; i < 6; ++i) F[0][i] = F1[i];
+    for (int i = 0; i < N; ++i) F[0][i] = F1[i];
 #pragma unroll
     for (int st = 1; st < NS; ++st) {
-        double X[6];
+        double X[N];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < N; ++i) {
             double acc = 0.0;
 #pragma unroll
             for (int l = 0; l < NS; ++l)
                 if (l < st && T.q[st][l] != 0.0) acc = fma(T.q[st][l], F[l][i], acc);
             X[i] = fma(GG(i), acc, fma(h * d8tab::C[st] * IM(i), p[i], x[i]));
         }
-        force<K0, K1, K2>(S, X, F[st], junk);
+        force_w<W, K0, K1, K2>(S, R, X, F[st], junk);
     }
-    double ex5[6], ex3[6], ep5[6], ep3[6];
+    double ex5[N], ex3[N], ep5[N], ep3[N];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < N; ++i) {
         double sx = 0.0, sp = 0.0, a5 = 0.0, a3 = 0.0, b5 = 0.0, b3 = 0.0;
 #pragma unroll
         for (int l = 0; l < NS; ++l) {
@@ -498,18 +618,26 @@ QD double dop853_trial(const Sys& S, const double* x, const double* p, const dou
     }
 #undef IM
 #undef GG
-    force<K0, K1, K2>(S, xn, F13, s2);
-    double n5 = 0.0, n3 = 0.0;
+    force_w<W, K0, K1, K2>(S, R, xn, F13, s2);
+    double part5[NC], part3[NC];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        const double e5p = h * fma(d8tab::E5[NS], F13[i], ep5[i]);
-        const double e3p = h * fma(d8tab::E3[NS], F13[i], ep3[i]);
-        const double isx = rcp_nr(fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol));
-        const double isp = rcp_nr(fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol));
-        const double a = ex5[i] * isx, b = e5p * isp, c = ex3[i] * isx, d = e3p * isp;
-        n5 = fma(a, a, fma(b, b, n5));
-        n3 = fma(c, c, fma(d, d, n3));
+    for (int c = 0; c < NC; ++c) {
+        double n5 = 0.0, n3 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = c + k * NC;
+            const double e5p = h * fma(d8tab::E5[NS], F13[i], ep5[i]);
+            const double e3p = h * fma(d8tab::E3[NS], F13[i], ep3[i]);
+            const double isx = rcp_nr(fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol));
+            const double isp = rcp_nr(fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol));
+            const double a = ex5[i] * isx, b = e5p * isp, cc = ex3[i] * isx, d = e3p * isp;
+            n5 = fma(a, a, fma(b, b, n5));
+            n3 = fma(cc, cc, fma(d, d, n3));
+        }
+        part5[c] = n5;
+        part3[c] = n3;
     }
+    const double n5 = comp_sum<W>(R, part5), n3 = comp_sum<W>(R, part3);
     if (n5 == 0.0 && n3 == 0.0) return 0.0;
     return n5 / sqrt((n5 + 0.01 * n3) * 12.0);
 }
@@ -552,36 +680,41 @@ QD double initial_step(const Sys& S, const double* x, const double* p, const dou
 }
 
 // ---------------------------------------------------------------------------
-// Per-lane trajectory state kept in registers while in flight.
+// Per-lane trajectory state kept in registers while in flight (the lane's
+// components only in the quad layout; the scalars in every lane).
 // ---------------------------------------------------------------------------
-struct Lane {
-    double x[6], p[6], F[6];
+template <int W>
+struct LaneW {
+    double x[2 * Lay<W>::NC], p[2 * Lay<W>::NC], F[2 * Lay<W>::NC];
     double t, tmax, rstop2, h;
     int32_t nstep, nrej, status, last_rej;
 };
+using Lane = LaneW<1>;
 
-// Advance one lane by one trial step with the paper's adaptive RK5(4) and the
-// stop rules (READING of Sec. 3.1: stop after the first accepted step with
-// the largest pair distance beyond r_stop_eff -- squares compared --, or at
-// t_max; fail on step count, non-finite state, step-size underflow, or a pair
-// inside a Buckingham inner maximum).  Step control: accept iff err <= 1,
-// h <- h min(10, max(0.2, 0.9 err^-1/5)), no increase right after a rejection,
-// h_min = 1e-12 t_max.
-template <int K0, int K1, int K2, int RK = 0>
-QD void lane_step(const Sys& S, const Prm& P, Lane& L)
+// Advance one trajectory by one trial step of the adaptive RK integrator and
+// apply the stop rules (READING of Sec. 3.1: stop after the first accepted
+// step with the largest pair distance beyond r_stop_eff -- squares compared
+// --, or at t_max; fail on step count, non-finite state, step-size
+// underflow, or a pair inside a Buckingham inner maximum).  Step control:
+// accept iff err <= 1, h <- h min(10, max(0.2, 0.9 err^-1/(q+1))), no
+// increase right after a rejection, h_min = 1e-12 t_max.  In the quad
+// layout all four lanes take the same decisions from the same values.
+template <int W, int K0, int K1, int K2, int RK = 0>
+QD void lane_step_w(const Sys& S, const Role& R, const Prm& P, LaneW<W>& L)
 {
-    double xn[6], pn[6], Fn[6], s2[3];
+    constexpr int N = 2 * Lay<W>::NC;
+    double xn[N], pn[N], Fn[N], s2[3];
     const double span = L.tmax - L.t;
     const double hs = fmin(L.h, span);
     double err = RK == 1
-                     ? dop853_trial<K0, K1, K2>(S, L.x, L.p, L.F, hs, P.atol, P.rtol, xn, pn, Fn, s2)
-                     : dopri5_trial<K0, K1, K2>(S, L.x, L.p, L.F, hs, P.atol, P.rtol, xn, pn, Fn, s2);
+        ? dop853_trial<W, K0, K1, K2>(S, R, L.x, L.p, L.F, hs, P.atol, P.rtol, xn, pn, Fn, s2)
+        : dopri5_trial<W, K0, K1, K2>(S, R, L.x, L.p, L.F, hs, P.atol, P.rtol, xn, pn, Fn, s2);
     if (P.fixed_step) err = 0.0;
     if (!(err <= 1.0e300)) err = INFINITY;   // NaN or inf: reject
     if (err <= 1.0) {
         L.t = (hs == span) ? L.tmax : L.t + hs;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < N; ++i) {
             L.x[i] = xn[i];
             L.p[i] = pn[i];
             L.F[i] = Fn[i];
@@ -589,7 +722,8 @@ QD void lane_step(const Sys& S, const Prm& P, Lane& L)
         L.nstep += 1;
         bool finite = true;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) finite = finite && is_finite(xn[i]) && is_finite(pn[i]);
+        for (int i = 0; i < N; ++i) finite = finite && is_finite(xn[i]) && is_finite(pn[i]);
+        if constexpr (W == 4) finite = quad_and(finite ? 1 : 0) != 0;
         const double m2 = fmax(s2[0], fmax(s2[1], s2[2]));
         const bool collapsed = s2[0] < S.rin2[0] || s2[1] < S.rin2[1] || s2[2] < S.rin2[2];
         if (!finite) L.status = FAIL_NONFINITE;
@@ -609,6 +743,12 @@ QD void lane_step(const Sys& S, const Prm& P, Lane& L)
     }
     if (L.status == RUNNING && !P.fixed_step && L.h < 1e-12 * L.tmax) L.status = FAIL_HMIN;
     if (L.status == RUNNING && L.nstep >= P.max_steps) L.status = FAIL_MAXSTEPS;
+}
+
+template <int K0, int K1, int K2, int RK = 0>
+QD void lane_step(const Sys& S, const Prm& P, Lane& L)
+{
+    lane_step_w<1, K0, K1, K2, RK>(S, Role{}, P, L);
 }
 
 // ---------------------------------------------------------------------------

@@ -73,10 +73,11 @@ class StateC(C.Structure):
 
 class RunOpts(C.Structure):
     _fields_ = [("blocks", C.c_int32), ("refill_min", C.c_int32), ("check_every", C.c_int32),
-                ("lpt", C.c_int32), ("graph", C.c_int32), ("rk", C.c_int32)]
+                ("lpt", C.c_int32), ("graph", C.c_int32), ("rk", C.c_int32),
+                ("lanes", C.c_int32), ("pad", C.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
 
 
 class OutcomeC(C.Structure):

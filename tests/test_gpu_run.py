@@ -1,9 +1,9 @@
 """GPU tests of the fused persistent run (qcams_run): per-trajectory results
 are a pure function of the trajectory id whatever the schedule (grid size,
-refill threshold, check interval, instance order); graph replays equal the
-eager run; the autotuner returns a valid option set; cross sections agree
-with the oracle within 3 combined standard errors and with the unfused
-ABI path."""
+refill threshold, check interval, instance order, one lane or a quad of
+lanes per trajectory); graph replays equal the eager run; the autotuner
+returns a valid option set; cross sections agree with the oracle within 3
+combined standard errors; the run equals the unfused ABI path."""
 import math
 
 import numpy as np
@@ -60,8 +60,11 @@ def test_run_is_schedule_independent(Q, torch, rk):
     ctx.set_instances(wl.instances)
     buf = ctx.new_run_buffers()
     ref = None
-    for blocks, rm, ce, lpt in [(0, 1, 1, 1), (3, 1, 1, 1), (5, 64, 1, 0), (2, 8, 7, 1), (1, 1, 3, 0)]:
-        o = Q.RunOpts(blocks=blocks, refill_min=rm, check_every=ce, lpt=lpt, graph=0, rk=rk)
+    for blocks, rm, ce, lpt, lanes in [(0, 1, 1, 1, 4), (3, 1, 1, 1, 1), (5, 64, 1, 0, 4),
+                                       (2, 8, 7, 1, 1), (1, 1, 3, 0, 4), (7, 3, 2, 1, 4),
+                                       (0, 1, 8, 1, 1)]:
+        o = Q.RunOpts(blocks=blocks, refill_min=rm, check_every=ce, lpt=lpt, graph=0, rk=rk,
+                      lanes=lanes)
         ctx.run(buf, o)
         torch.cuda.synchronize()
         snap = _snapshot(buf)
@@ -87,10 +90,9 @@ def test_run_is_schedule_independent(Q, torch, rk):
 
 
 def test_run_agrees_with_unfused_path(Q, torch):
-    """Same trajectories through init / propagate / classify / cross sections:
-    per-trajectory labels agree (chaotic trajectories may part company at the
-    rounding level, so a small fraction is allowed to differ) and cross
-    sections agree within their errors."""
+    """Same trajectories through init / propagate / classify / cross sections
+    (one lane per trajectory) and through the fused run (quads): identical
+    per-trajectory results, cross sections equal to rounding."""
     wl = _mixed_energy_workload(per=200)
     ctx = Q.Context(wl.system, wl.params)
     ctx.set_instances(wl.instances)
@@ -105,12 +107,47 @@ def test_run_agrees_with_unfused_path(Q, torch):
     ctx.classify(st, out)
     xs, _ = ctx.cross_sections(out, tid)
     torch.cuda.synchronize()
-    agree = (out.label.cpu().numpy() == buf["outcome"].label.cpu().numpy()).mean()
-    assert agree > 0.9, agree
-    a, b = xs.cpu().numpy(), buf["xs"].cpu().numpy()
-    for c in range(4):
-        comb = np.sqrt(a[:, 19 + c] ** 2 + b[:, 19 + c] ** 2)
-        assert np.all(np.abs(a[:, 15 + c] - b[:, 15 + c]) <= 3 * comb + 1e-12), c
+    r = _snapshot(buf)
+    assert np.array_equal(st.d.cpu().numpy(), r["d"])
+    assert np.array_equal(st.nstep.cpu().numpy(), r["nstep"])
+    assert np.array_equal(st.nrej.cpu().numpy(), r["nrej"])
+    assert np.array_equal(st.status.cpu().numpy(), r["status"])
+    assert np.array_equal(out.label.cpu().numpy(), r["label"])
+    assert np.array_equal(out.vt.cpu().numpy(), r["vt"])
+    assert np.array_equal(out.jt.cpu().numpy(), r["jt"])
+    assert np.array_equal(out.d.cpu().numpy(), r["od"], equal_nan=True)
+    a, b = xs.cpu().numpy(), r["xs"]
+    assert np.allclose(a, b, rtol=1e-13, atol=0.0)
+
+
+def _system_cases():
+    s = W.h2ca_system()
+    bc = W.Pair("buck", {"A": 50.0, "b": 1.5, "C6": 40.0})
+    generic = W.System(s.masses_amu, (s.pairs[0], bc, s.pairs[2]), "h2 generic")
+    mixed = W.config_mixed(per_inst=2)
+    return {"all_morse": (s, _mixed_energy_workload(per=40).instances),
+            "lj_morse_buck": (mixed.system, mixed.instances[::40]),
+            "generic": (generic, _mixed_energy_workload(per=40).instances)}
+
+
+@pytest.mark.parametrize("case", ["all_morse", "lj_morse_buck", "generic"])
+@pytest.mark.parametrize("rk", [1, 2], ids=["dopri5", "dop853"])
+def test_quad_lanes_equal_single_lane(Q, torch, case, rk):
+    """The quad layout (four lanes per trajectory, DPP exchanges) gives the
+    same bits as one lane per trajectory, for every kernel specialisation
+    and both RK variants."""
+    system, inst = _system_cases()[case]
+    ctx = Q.Context(system, W.Params())
+    ctx.set_instances(inst)
+    buf = ctx.new_run_buffers()
+    snaps = []
+    for lanes in (1, 4):
+        ctx.run(buf, Q.RunOpts(refill_min=1, check_every=4, lpt=1, graph=0, rk=rk, lanes=lanes))
+        torch.cuda.synchronize()
+        snaps.append(_snapshot(buf))
+    _same(snaps[0], snaps[1])
+    assert np.all(snaps[0]["status"] != Q.RUNNING)
+    print(case, "labels", np.bincount(snaps[0]["label"], minlength=6))
 
 
 def test_graph_replays_match_eager(Q, torch):
@@ -141,6 +178,7 @@ def test_autotune_returns_valid_options(Q, torch, search_rk):
     best, ms = ctx.autotune(buf, reps=1, search_rk=search_rk, energy_gate=1e-8)
     assert ms > 0 and best.blocks > 0 and 1 <= best.refill_min <= 64 and best.check_every >= 1
     assert best.rk in ((1, 2) if search_rk else (0,))
+    assert best.lanes in (1, 4)
     ctx.run(buf, Q.RunOpts(graph=0, refill_min=1, check_every=1, lpt=1, rk=best.rk))
     torch.cuda.synchronize()
     ref = _snapshot(buf)
