@@ -280,19 +280,21 @@ QD Role make_role(const Sys& S, int c)
 constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E;
 template <int K> struct Bc { static constexpr int ctrl = K * 0x55; };
 
+// (bound_ctrl set: no lane reads outside its quad, so no "old" value is
+// needed and none is materialised)
 template <int CTRL>
 __device__ inline double quad_perm(double v)
 {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 __device__ inline int quad_and(int v)
 {
-    v &= __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false);
-    return v & __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, false);
+    v &= __builtin_amdgcn_mov_dpp(v, kDppXor1, 0xF, 0xF, true);
+    return v & __builtin_amdgcn_mov_dpp(v, kDppXor2, 0xF, 0xF, true);
 }
 
 // (s_0 + s_1) + (s_2 + s_3) over the quad, the same value in all four lanes
@@ -442,6 +444,48 @@ constexpr double z5 = e6 * a65 + e7 * b5;
 constexpr double z6 = e7 * b6;
 }  // namespace dp
 
+// ---------------------------------------------------------------------------
+// RK coefficients in constant memory.  A step reads them through a pointer
+// made opaque to the compiler once per step (an empty asm on it), so they
+// are fetched inside the step loop with wide scalar loads (16 dwords per
+// instruction) rather than held live across the loop, where they exceed the
+// scalar registers and spill.  Each table lists the nonzero coefficients in
+// the order the step uses them, so consecutive reads merge.
+// ---------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef __attribute__((address_space(4))) const double kcoef_t;
+#else
+typedef const double kcoef_t;
+#endif
+
+namespace dp {
+enum : int {
+    C2, C3, Q31, C4, Q41, Q42, C5, Q51, Q52, Q53, Q61, Q62, Q63, Q64,
+    W1, W2, W3, W4, W5, B1, B3, B4, B5, B6, Z1, Z2, Z3, Z4, Z5, Z6,
+    E1, E3, E4, E5, E6, E7, NV
+};
+struct Vals { double v[NV]; };
+constexpr Vals vals()
+{
+    return Vals{{c2, c3, q31, c4, q41, q42, c5, q51, q52, q53, q61, q62, q63, q64,
+                 w1, w2, w3, w4, w5, b1, b3, b4, b5, b6, z1, z2, z3, z4, z5, z6,
+                 e1, e3, e4, e5, e6, e7}};
+}
+constexpr Vals VALS = vals();
+}  // namespace dp
+__constant__ dp::Vals kDp = dp::vals();
+
+QD kcoef_t* dp_coefs()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    kcoef_t* k = (kcoef_t*)&kDp.v[0];
+    asm volatile("" : "+s"(k));
+    return k;
+#else
+    return &dp::VALS.v[0];
+#endif
+}
+
 // Sum over the spatial components c of per-component partial sums, in the
 // tree shared by both layouts (lane 3 of a quad contributes +0).
 template <int W>
@@ -465,6 +509,7 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
 {
     using namespace dp;
     constexpr int NC = Lay<W>::NC, N = 2 * NC;
+    kcoef_t* K = dp_coefs();
     double X[N], F2[N], F3[N], F4[N], F5[N], F6[N], junk[3];
     const double hh = h * h;
     // per-component 1/mu (uniform) and h^2/mu
@@ -473,24 +518,24 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
 #define IM(i) ((i) < NC ? im0 : im1)
 #define GG(i) ((i) < NC ? g0 : g1)
 #pragma unroll
-    for (int i = 0; i < N; ++i) X[i] = fma(h * c2 * IM(i), p[i], x[i]);
+    for (int i = 0; i < N; ++i) X[i] = fma(h * K[C2] * IM(i), p[i], x[i]);
     force_w<W, K0, K1, K2>(S, R, X, F2, junk);
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        X[i] = fma(GG(i), q31 * F1[i], fma(h * c3 * IM(i), p[i], x[i]));
+        X[i] = fma(GG(i), K[Q31] * F1[i], fma(h * K[C3] * IM(i), p[i], x[i]));
     force_w<W, K0, K1, K2>(S, R, X, F3, junk);
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        X[i] = fma(GG(i), fma(q42, F2[i], q41 * F1[i]), fma(h * c4 * IM(i), p[i], x[i]));
+        X[i] = fma(GG(i), fma(K[Q42], F2[i], K[Q41] * F1[i]), fma(h * K[C4] * IM(i), p[i], x[i]));
     force_w<W, K0, K1, K2>(S, R, X, F4, junk);
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        X[i] = fma(GG(i), fma(q53, F3[i], fma(q52, F2[i], q51 * F1[i])),
-                   fma(h * c5 * IM(i), p[i], x[i]));
+        X[i] = fma(GG(i), fma(K[Q53], F3[i], fma(K[Q52], F2[i], K[Q51] * F1[i])),
+                   fma(h * K[C5] * IM(i), p[i], x[i]));
     force_w<W, K0, K1, K2>(S, R, X, F5, junk);
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        X[i] = fma(GG(i), fma(q64, F4[i], fma(q63, F3[i], fma(q62, F2[i], q61 * F1[i]))),
+        X[i] = fma(GG(i), fma(K[Q64], F4[i], fma(K[Q63], F3[i], fma(K[Q62], F2[i], K[Q61] * F1[i]))),
                    fma(h * IM(i), p[i], x[i]));
     force_w<W, K0, K1, K2>(S, R, X, F6, junk);
     // step and error estimate (all but the F7 term) before the last force,
@@ -498,13 +543,13 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
     double ep[N], ex[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        xn[i] = fma(GG(i), fma(w5, F5[i], fma(w4, F4[i], fma(w3, F3[i], fma(w2, F2[i], w1 * F1[i])))),
+        xn[i] = fma(GG(i), fma(K[W5], F5[i], fma(K[W4], F4[i], fma(K[W3], F3[i], fma(K[W2], F2[i], K[W1] * F1[i])))),
                     fma(h * IM(i), p[i], x[i]));
-        pn[i] = fma(h, fma(b6, F6[i], fma(b5, F5[i], fma(b4, F4[i], fma(b3, F3[i], b1 * F1[i])))),
+        pn[i] = fma(h, fma(K[B6], F6[i], fma(K[B5], F5[i], fma(K[B4], F4[i], fma(K[B3], F3[i], K[B1] * F1[i])))),
                     p[i]);
-        ex[i] = GG(i) * fma(z6, F6[i], fma(z5, F5[i], fma(z4, F4[i],
-                            fma(z3, F3[i], fma(z2, F2[i], z1 * F1[i])))));
-        ep[i] = fma(e6, F6[i], fma(e5, F5[i], fma(e4, F4[i], fma(e3, F3[i], e1 * F1[i]))));
+        ex[i] = GG(i) * fma(K[Z6], F6[i], fma(K[Z5], F5[i], fma(K[Z4], F4[i],
+                            fma(K[Z3], F3[i], fma(K[Z2], F2[i], K[Z1] * F1[i])))));
+        ep[i] = fma(K[E6], F6[i], fma(K[E5], F5[i], fma(K[E4], F4[i], fma(K[E3], F3[i], K[E1] * F1[i]))));
     }
 #undef IM
 #undef GG
@@ -516,7 +561,7 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int i = c + k * NC;
-            const double epi = h * fma(e7, F7[i], ep[i]);
+            const double epi = h * fma(K[E7], F7[i], ep[i]);
             const double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
             const double sp = fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol);
             const double qx = ex[i] * rcp_nr(sx), qp = epi * rcp_nr(sp);
@@ -568,6 +613,73 @@ constexpr Derived derive()
 constexpr Derived T = derive();
 }  // namespace d8
 
+namespace d8 {
+// positions of the nonzero coefficients in the constant table (-1: zero)
+constexpr int NV = 256;
+struct Index {
+    int16_t c[NS], q[NS][NS], bA[NS], b[NS], e5A[NS], e3A[NS], e5[NS], e3[NS];
+    int16_t e5_13, e3_13, n;
+};
+struct Vals { double v[NV]; };
+constexpr Index index()
+{
+    Index x{};
+    int k = 0;
+    for (int st = 0; st < NS; ++st) {
+        x.c[st] = (int16_t)k++;
+        for (int l = 0; l < NS; ++l)
+            x.q[st][l] = (int16_t)((l < st && T.q[st][l] != 0.0) ? k++ : -1);
+    }
+    for (int l = 0; l < NS; ++l) {
+        x.bA[l] = (int16_t)(T.bA[l] != 0.0 ? k++ : -1);
+        x.b[l] = (int16_t)(d8tab::B[l] != 0.0 ? k++ : -1);
+        x.e5A[l] = (int16_t)(T.e5A[l] != 0.0 ? k++ : -1);
+        x.e3A[l] = (int16_t)(T.e3A[l] != 0.0 ? k++ : -1);
+        x.e5[l] = (int16_t)(d8tab::E5[l] != 0.0 ? k++ : -1);
+        x.e3[l] = (int16_t)(d8tab::E3[l] != 0.0 ? k++ : -1);
+    }
+    x.e5_13 = (int16_t)k++;
+    x.e3_13 = (int16_t)k++;
+    x.n = (int16_t)k;
+    return x;
+}
+constexpr Index IX = index();
+static_assert(IX.n <= NV, "coefficient table too small");
+constexpr Vals vals()
+{
+    Vals v{};
+    for (int st = 0; st < NS; ++st) {
+        v.v[IX.c[st]] = d8tab::C[st];
+        for (int l = 0; l < NS; ++l)
+            if (IX.q[st][l] >= 0) v.v[IX.q[st][l]] = T.q[st][l];
+    }
+    for (int l = 0; l < NS; ++l) {
+        if (IX.bA[l] >= 0) v.v[IX.bA[l]] = T.bA[l];
+        if (IX.b[l] >= 0) v.v[IX.b[l]] = d8tab::B[l];
+        if (IX.e5A[l] >= 0) v.v[IX.e5A[l]] = T.e5A[l];
+        if (IX.e3A[l] >= 0) v.v[IX.e3A[l]] = T.e3A[l];
+        if (IX.e5[l] >= 0) v.v[IX.e5[l]] = d8tab::E5[l];
+        if (IX.e3[l] >= 0) v.v[IX.e3[l]] = d8tab::E3[l];
+    }
+    v.v[IX.e5_13] = d8tab::E5[NS];
+    v.v[IX.e3_13] = d8tab::E3[NS];
+    return v;
+}
+constexpr Vals VALS = vals();
+}  // namespace d8
+__constant__ d8::Vals kD8 = d8::vals();
+
+QD kcoef_t* d8_coefs()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    kcoef_t* k = (kcoef_t*)&kD8.v[0];
+    asm volatile("" : "+s"(k));
+    return k;
+#else
+    return &d8::VALS.v[0];
+#endif
+}
+
 template <int W, int K0, int K1, int K2>
 QD double dop853_trial(const Sys& S, const Role& R, const double* x, const double* p,
                        const double* F1, double h, double atol, double rtol, double* xn,
@@ -575,6 +687,7 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
 {
     using namespace d8;
     constexpr int NC = Lay<W>::NC, N = 2 * NC;
+    kcoef_t* K = d8_coefs();
     double F[NS][N], junk[3];
     const double hh = h * h;
     const double im0 = S.inv_mu12, im1 = S.inv_mu123;
@@ -591,8 +704,8 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
             double acc = 0.0;
 #pragma unroll
             for (int l = 0; l < NS; ++l)
-                if (l < st && T.q[st][l] != 0.0) acc = fma(T.q[st][l], F[l][i], acc);
-            X[i] = fma(GG(i), acc, fma(h * d8tab::C[st] * IM(i), p[i], x[i]));
+                if (IX.q[st][l] >= 0) acc = fma(K[IX.q[st][l]], F[l][i], acc);
+            X[i] = fma(GG(i), acc, fma(h * K[IX.c[st]] * IM(i), p[i], x[i]));
         }
         force_w<W, K0, K1, K2>(S, R, X, F[st], junk);
     }
@@ -602,12 +715,12 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
         double sx = 0.0, sp = 0.0, a5 = 0.0, a3 = 0.0, b5 = 0.0, b3 = 0.0;
 #pragma unroll
         for (int l = 0; l < NS; ++l) {
-            if (T.bA[l] != 0.0) sx = fma(T.bA[l], F[l][i], sx);
-            if (d8tab::B[l] != 0.0) sp = fma(d8tab::B[l], F[l][i], sp);
-            if (T.e5A[l] != 0.0) a5 = fma(T.e5A[l], F[l][i], a5);
-            if (T.e3A[l] != 0.0) a3 = fma(T.e3A[l], F[l][i], a3);
-            if (d8tab::E5[l] != 0.0) b5 = fma(d8tab::E5[l], F[l][i], b5);
-            if (d8tab::E3[l] != 0.0) b3 = fma(d8tab::E3[l], F[l][i], b3);
+            if (IX.bA[l] >= 0) sx = fma(K[IX.bA[l]], F[l][i], sx);
+            if (IX.b[l] >= 0) sp = fma(K[IX.b[l]], F[l][i], sp);
+            if (IX.e5A[l] >= 0) a5 = fma(K[IX.e5A[l]], F[l][i], a5);
+            if (IX.e3A[l] >= 0) a3 = fma(K[IX.e3A[l]], F[l][i], a3);
+            if (IX.e5[l] >= 0) b5 = fma(K[IX.e5[l]], F[l][i], b5);
+            if (IX.e3[l] >= 0) b3 = fma(K[IX.e3[l]], F[l][i], b3);
         }
         xn[i] = fma(GG(i), sx, fma(h * IM(i), p[i], x[i]));
         pn[i] = fma(h, sp, p[i]);
@@ -626,8 +739,8 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int i = c + k * NC;
-            const double e5p = h * fma(d8tab::E5[NS], F13[i], ep5[i]);
-            const double e3p = h * fma(d8tab::E3[NS], F13[i], ep3[i]);
+            const double e5p = h * fma(K[IX.e5_13], F13[i], ep5[i]);
+            const double e3p = h * fma(K[IX.e3_13], F13[i], ep3[i]);
             const double isx = rcp_nr(fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol));
             const double isp = rcp_nr(fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol));
             const double a = ex5[i] * isx, b = e5p * isp, cc = ex3[i] * isx, d = e3p * isp;
