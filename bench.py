@@ -27,11 +27,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# FP64 operations per trial step of one trajectory on the all-Morse surface
-# (FMA = 2), counted with hardware FP64 instruction counters on a full-wave
-# fixed-step run of the propagation kernel, per RK variant.
-F_STEP_MORSE = {0: 1969.4, 1: 4342.4}
+# FP64 operations per trial step of one trajectory (FMA = 2), counted with
+# hardware FP64 instruction counters on a full-wave fixed-step run of the
+# one-lane propagation kernel, per surface and RK variant.
+F_STEP = {("morse", 0): 1969.4, ("morse", 1): 4342.4,
+          ("mixed", 0): None, ("mixed", 1): None}
 RK_NAMES = {"dopri5": 0, "dop853": 1}
+KINDS = {"morse": "0,0,0", "mixed": "1,0,2"}
+# workload -> (surface, default CPU-baseline stride)
+WORKLOADS = {"batched": ("morse", 25), "small": ("morse", 1), "mixed": ("mixed", 500),
+             "sweep": ("morse", 5000)}
 PEAK_FP64_VECTOR = 78.6e12   # MI355X, FLOP/s
 
 
@@ -40,9 +45,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=["batched", "small"])
-    ap.add_argument("--cpu-stride", type=int, default=25,
-                    help="CPU baseline runs every k-th trajectory id through the oracle")
+    ap.add_argument("--workload", default="batched", choices=list(WORKLOADS))
+    ap.add_argument("--cpu-stride", type=int, default=0,
+                    help="CPU baseline runs every k-th trajectory id through the oracle "
+                         "(0: the workload's default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-procs", type=int, default=16)
     ap.add_argument("--rk", default="dop853", choices=list(RK_NAMES),
@@ -55,8 +61,8 @@ def parse():
     ap.add_argument("--refill-min", type=int, default=1)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-lpt", action="store_true")
-    ap.add_argument("--lanes", type=int, default=4, choices=[1, 4],
-                    help="lanes per trajectory in the persistent kernel")
+    ap.add_argument("--lanes", type=int, default=0, choices=[0, 1, 4],
+                    help="lanes per trajectory in the persistent kernel (0: by run size)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--learned", action="store_true",
                     help="also train the proposal network and report variance x GPU-seconds, "
@@ -100,7 +106,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    wl = W.config_batched() if args.workload == "batched" else W.config_small()
+    wl = W.CONFIGS[args.workload]()
+    surface, stride = WORKLOADS[args.workload]
     rk = RK_NAMES[args.rk]
     wl.params = dataclasses.replace(wl.params, rk=rk)
     dev = torch.device("cuda", 0)
@@ -161,12 +168,13 @@ def main():
     prop_ms = float(np.mean([t if isinstance(t, float) else t[0].elapsed_time(t[1])
                              for t in prop_times]))
 
+    used = ctx.last_run_options() if args.path == "run" else None
     # work of the last step
     nstep = st.nstep.cpu().numpy().astype(np.int64)
     nrej = st.nrej.cpu().numpy().astype(np.int64)
     per_traj = nstep + nrej
     trial_steps = int(per_traj.sum())
-    f_step = F_STEP_MORSE[rk]
+    f_step = F_STEP[(surface, rk)]
     achieved = trial_steps * f_step / (prop_ms * 1e-3) / 1e12 if f_step else None
     lab = out.label.cpu().numpy()
     dE = out.d[3].cpu().numpy()
@@ -185,18 +193,20 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "n_traj": n, "instances": len(wl.instances),
-                   "surface": "H2+Ca all-Morse", "integrator": args.rk, "atol": wl.params.atol,
+                   "surface": wl.system.name, "integrator": args.rk, "atol": wl.params.atol,
                    "rtol": wl.params.rtol, "R0": wl.params.R0, "t_stop": wl.params.t_stop,
                    "r_stop": wl.params.r_stop},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR / 1e12,
                      "unit": "TFLOP/s",
                      "frac": achieved * 1e12 / PEAK_FP64_VECTOR if achieved else None,
                      "traffic": None,
-                     "kernel": ("k_persistent<%d,0,0,0,%d>" % (args.lanes, rk)
-                                if args.path == "run" else "k_propagate<0,0,0,%d>" % rk),
+                     "kernel": ("k_persistent<%d,%s,%d>" % (used.lanes, KINDS[surface], rk)
+                                if args.path == "run"
+                                else "k_propagate<%s,%d>" % (KINDS[surface], rk)),
                      "timed_ms": prop_ms, "trial_steps": trial_steps,
                      "flop_per_trial_step": f_step},
-        "path": args.path, "run_opts": opts.as_dict(), "autotune": tuned,
+        "path": args.path, "run_opts": used.as_dict() if used else opts.as_dict(),
+        "autotune": tuned,
         "trial_steps_per_s": trial_steps / (ms_step * 1e-3),
         "trial_steps_per_traj": {q: int(np.percentile(per_traj, p)) for q, p in
                                  (("p50", 50), ("p90", 90), ("p99", 99), ("p999", 99.9),
@@ -208,7 +218,7 @@ def main():
     if args.learned:
         res["learned"] = learned_metric(args)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_stride, args.cpu_procs)
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_stride or stride, args.cpu_procs)
     print(json.dumps(res), flush=True)
 
 

@@ -234,8 +234,10 @@ typedef struct {
     int32_t graph;       /* 1: capture the launch sequence once per buffer set and replay it */
     int32_t rk;          /* 0: the context's variant; 1: DOPRI5; 2: DOP853 */
     int32_t lanes;       /* lanes per trajectory: 1, or 4 (a quad shares the arithmetic of one
-                            trajectory; 16 slots per wave); 0 = 4.  Both give bit-identical
-                            trajectories; 4 cuts the latency of each step to about 40 % */
+                            trajectory; 16 slots per wave).  Both give bit-identical
+                            trajectories; 4 halves the latency of a step, 1 doubles the
+                            throughput.  0: 4 if the run has at most 4 trajectories per lane
+                            of a one-lane grid (bound by its longest trajectories), else 1 */
     int32_t pad;
 } qcams_run_opts;
 
@@ -249,7 +251,7 @@ typedef struct {
  * ids[p] (device int64 [N], written) as the matching trajectory id.  xs,
  * hist (may be NULL) as in qcams_cross_sections.  opts may be NULL
  * (defaults: 1 workgroup per CU, refill_min 1, check_every 8, LPT, no
- * graph, the context's RK variant, 4 lanes per trajectory).  Per-trajectory
+ * graph, the context's RK variant, lanes chosen by run size).  Per-trajectory
  * results do not depend on blocks, refill_min, check_every, lpt, graph or
  * lanes.  With opts->graph the small set-up and analysis launches around
  * the persistent kernel are captured into two HIP graphs on first use (per
@@ -264,6 +266,11 @@ int qcams_run(qcams_ctx *ctx, const qcams_run_opts *opts, const qcams_state *st,
  * the run's stream (also when the run was a graph replay).  Waits for the
  * run to finish.  sync.  Errors: EINVAL (no run yet), EHIP. */
 int qcams_last_run_kernel_ms(qcams_ctx *ctx, double *ms);
+
+/* The options the last qcams_run on this context took effect with: blocks,
+ * refill_min and check_every as clamped, rk = 1 (DOPRI5) or 2 (DOP853),
+ * lanes = 1 or 4.  host only.  Errors: EINVAL (no run yet). */
+int qcams_last_run_options(qcams_ctx *ctx, qcams_run_opts *used);
 
 /* Choose fast qcams_run options on the installed instances -- install a
  * calibration subset first -- by timing runs: coordinate descent, two

@@ -37,6 +37,8 @@ struct qcams_ctx {
     int64_t* d_order = nullptr;                // [n_total] work item -> natural position
     int64_t order_cap = 0;
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
+    qcams_run_opts last_opts{};                   // effective options of the last run
+    bool has_run = false;
     // importance-sampling proposal (cells of b^2, chi, cos theta)
     double* d_prop_q = nullptr;
     double* d_prop_cdf = nullptr;
@@ -1010,10 +1012,15 @@ static int run_variant(const qcams_ctx* c, const qcams_run_opts* o)
     return o->rk == 1 ? 0 : (o->rk == 2 ? 1 : c->prm.rk);
 }
 
-// lanes per trajectory of the persistent kernel (default: a quad)
-static int run_width(const qcams_run_opts* o)
+// Lanes per trajectory of the persistent kernel.  Default: a quad when the
+// run has at most four trajectories per lane of a one-lane grid (the run is
+// then bound by its longest trajectories, whose steps the quad shortens),
+// else one lane (the run is bound by throughput, which one lane maximises).
+static int run_width(const qcams_ctx* c, const qcams_run_opts* o)
 {
-    return o->lanes == 1 ? 1 : 4;
+    if (o->lanes == 1 || o->lanes == 4) return o->lanes;
+    const int64_t blocks = o->blocks > 0 ? o->blocks : c->n_cu;
+    return c->n_total <= 4 * blocks * 256 ? 4 : 1;
 }
 
 // The run is three launch groups: the small set-up kernels (work order,
@@ -1037,12 +1044,21 @@ static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const qcams
                               hipStream_t s)
 {
     const int blocks = o->blocks > 0 ? o->blocks : c->n_cu;
-    const int slots = 64 / run_width(o);
+    const int width = run_width(c, o);
+    const int slots = 64 / width;
     const int rm = o->refill_min < 1 ? 1 : (o->refill_min > slots ? slots : o->refill_min);
     const int ce = o->check_every < 1 ? 1 : o->check_every;
     if (hipEventRecord(c->ev_prop[0], s) != hipSuccess) return QCAMS_EHIP;
-    with_variant<PersistentL>(c, run_variant(c, o), c, run_width(o), blocks, rm, ce,
+    with_variant<PersistentL>(c, run_variant(c, o), c, width, blocks, rm, ce,
                               (const int64_t*)c->d_order, st, s);
+    c->last_opts = *o;
+    c->last_opts.blocks = blocks;
+    c->last_opts.refill_min = rm;
+    c->last_opts.check_every = ce;
+    c->last_opts.rk = run_variant(c, o) + 1;
+    c->last_opts.lanes = width;
+    c->last_opts.pad = 0;
+    c->has_run = true;
     if (hipEventRecord(c->ev_prop[1], s) != hipSuccess) return QCAMS_EHIP;
     return hipGetLastError() == hipSuccess ? QCAMS_OK : QCAMS_EHIP;
 }
@@ -1286,6 +1302,14 @@ int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out
     if (rc != QCAMS_OK) return rc == QCAMS_EHIP ? fail(c, rc, "autotune run failed") : rc;
     *best = bo;
     if (best_ms) *best_ms = best_t;
+    return QCAMS_OK;
+}
+
+int qcams_last_run_options(qcams_ctx* c, qcams_run_opts* used)
+{
+    if (!c || !used) return fail(c, QCAMS_EINVAL, "null argument");
+    if (!c->has_run) return fail(c, QCAMS_EINVAL, "no run recorded");
+    *used = c->last_opts;
     return QCAMS_OK;
 }
 

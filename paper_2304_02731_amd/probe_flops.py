@@ -26,13 +26,14 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--h", type=float, default=0.25)
     ap.add_argument("--rk", type=int, default=0, help="0: DOPRI5, 1: DOP853")
+    ap.add_argument("--workload", default="batched", choices=["batched", "mixed"])
     args = ap.parse_args()
     import torch
 
     import qcams_workloads as W
     import paper_2304_02731_amd as Q
 
-    wl = W.config_batched()
+    wl = W.CONFIGS[args.workload]()
     prm = dataclasses.replace(wl.params, fixed_step=1, h_fixed=args.h, rk=args.rk)
     ctx = Q.Context(wl.system, prm, device=0)
     ctx.set_instances(wl.instances)
@@ -50,7 +51,7 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     ns = st.nstep.cpu()
-    print(json.dumps({"rk": args.rk, "lanes": n, "steps_min": int(ns.min()), "steps_max": int(ns.max()),
+    print(json.dumps({"workload": wl.name, "rk": args.rk, "lanes": n, "steps_min": int(ns.min()), "steps_max": int(ns.max()),
                       "lane_steps": int(ns.sum()), "kernel_ms": e0.elapsed_time(e1)}), flush=True)
 
 

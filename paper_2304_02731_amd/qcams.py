@@ -119,6 +119,7 @@ def lib():
     L.qcams_run.argtypes = [vp, C.POINTER(RunOpts), C.POINTER(StateC), vp, C.POINTER(OutcomeC),
                             vp, vp, vp, vp]
     L.qcams_last_run_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
+    L.qcams_last_run_options.argtypes = [vp, C.POINTER(RunOpts)]
     L.qcams_autotune.argtypes = [vp, C.POINTER(StateC), C.POINTER(OutcomeC), vp, vp, i32, i32,
                                  C.c_double, C.POINTER(RunOpts), C.POINTER(C.c_double)]
     L.qcams_mlp_create.argtypes = [C.POINTER(vp), C.c_int, vp, C.c_uint64]
@@ -366,6 +367,12 @@ class Context:
         ms = C.c_double()
         self._check(lib().qcams_last_run_kernel_ms(self._h, C.byref(ms)), "qcams_last_run_kernel_ms")
         return ms.value
+
+    def last_run_options(self) -> RunOpts:
+        """Effective options of the last run (qcams_last_run_options)."""
+        o = RunOpts()
+        self._check(lib().qcams_last_run_options(self._h, C.byref(o)), "qcams_last_run_options")
+        return o
 
     def autotune(self, buf, reps: int = 1, search_rk: bool = False, energy_gate: float = 1e-8):
         """Fastest qcams_run options on the installed instances (qcams_autotune);
