@@ -31,7 +31,11 @@ if ROOT not in sys.path:
 # hardware FP64 instruction counters on a full-wave fixed-step run of the
 # one-lane propagation kernel, per surface and RK variant.
 F_STEP = {("morse", 0): 1969.4, ("morse", 1): 4342.4,
-          ("mixed", 0): None, ("mixed", 1): None}
+          ("mixed", 0): 1881.7, ("mixed", 1): 4194.7}
+# HBM bytes per launch of the persistent kernel from FETCH_SIZE and WRITE_SIZE
+# passes scaled by a streaming kernel of known size, for the kernel as it was
+# when the counters were taken (workload, kernel) -> bytes; null otherwise.
+TRAFFIC = {("batched", "k_persistent<4,0,0,0,1>"): 136.50e6}
 RK_NAMES = {"dopri5": 0, "dop853": 1}
 KINDS = {"morse": "0,0,0", "mixed": "1,0,2"}
 # workload -> (surface, default CPU-baseline stride)
@@ -199,7 +203,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR / 1e12,
                      "unit": "TFLOP/s",
                      "frac": achieved * 1e12 / PEAK_FP64_VECTOR if achieved else None,
-                     "traffic": None,
+                     "traffic": None,   # filled below
                      "kernel": ("k_persistent<%d,%s,%d>" % (used.lanes, KINDS[surface], rk)
                                 if args.path == "run"
                                 else "k_propagate<%s,%d>" % (KINDS[surface], rk)),
@@ -215,6 +219,7 @@ def main():
         "labels": np.bincount(lab, minlength=6).tolist(),
         "wall_s": wall,
     }
+    res["roofline"]["traffic"] = TRAFFIC.get((args.workload, res["roofline"]["kernel"]))
     if args.learned:
         res["learned"] = learned_metric(args)
     if not args.no_cpu_baseline:

@@ -8,6 +8,7 @@ import math
 
 import numpy as np
 import pytest
+from scipy import stats
 
 import qcams_workloads as W
 
@@ -225,3 +226,64 @@ def test_run_cross_sections_vs_oracle(Q, torch, orc):
         assert abs(xs[15 + c] - ref["sigma"][0, c]) <= 3 * comb + 1e-12, c
     print("sigma_q GPU %.4f +- %.4f  oracle %.4f +- %.4f" % (xs[15], xs[19], ref["sigma"][0, 0],
                                                            ref["dsigma"][0, 0]))
+
+
+def test_full_size_bench_configuration(Q, torch, orc):
+    """The 100,032-trajectory batched workload in the launch configuration the
+    benchmark times (DOP853, quads chosen by run size, LPT, graph): every
+    trajectory finishes inside the energy gate; sampled trajectories checked
+    one by one against the oracle (draws bit-exact, classification of the
+    GPU's own final state bit-exact); per-channel probabilities of the full
+    run against the oracle's on a stratified subsample (every 25th id of
+    every instance): within 3 combined standard errors pooled over instances,
+    and per instance the oracle's count is consistent with the GPU's
+    probability (two-sided exact binomial test, p > 1e-4 for each of the
+    384 instance-channel pairs)."""
+    import dataclasses
+    wl = W.config_batched()
+    wl.params = dataclasses.replace(wl.params, rk=W.RK_DOP853)
+    ctx = Q.Context(wl.system, wl.params)
+    ctx.set_instances(wl.instances)
+    buf = ctx.new_run_buffers()
+    ctx.run(buf, Q.RunOpts(graph=1, refill_min=1, check_every=8, lpt=1))
+    torch.cuda.synchronize()
+    used = ctx.last_run_options()
+    assert used.lanes == 4 and used.rk == 2 and used.blocks > 0
+    r = _snapshot(buf)
+    n = len(r["ids"])
+    assert n == 100032 and np.all(r["status"] != Q.RUNNING)
+    lab, xs = r["label"], r["xs"]
+    assert np.array_equal(xs[:, 0], [I.n_traj for I in wl.instances])
+    fin = lab != Q.FAILED
+    assert fin.mean() > 0.999
+    assert np.abs(r["od"][3][fin]).max() < 1e-8
+    sys, prm = orc.make_system(wl.system), orc.make_params(wl.params)
+    firsts = np.array([I.first_id for I in wl.instances])
+    which = np.searchsorted(firsts, r["ids"], side="right") - 1
+    rng = np.random.default_rng(5)
+    for c in rng.choice(n, 48, replace=False):
+        I = wl.instances[which[c]]
+        lev = orc.level(sys, I.v, I.j)
+        _, _, sm = orc.init(sys, prm, orc.make_instance(I), lev, int(r["ids"][c]))
+        assert np.array_equal(r["sample"][:5, c], sm[:5])
+        if fin[c]:
+            cl = orc.classify(sys, prm, r["d"][:12, c])
+            assert (cl["label"], cl["vt"], cl["jt"]) == (lab[c], r["vt"][c], r["jt"][c]), c
+    per = [np.arange(I.first_id, I.first_id + I.n_traj, 25, dtype=np.int64) for I in wl.instances]
+    recs, w2 = orc.run_workload(wl, per, processes=8)
+    ref = orc.cross_sections(wl, recs["label"], np.ones(len(recs)), w2)
+    m = np.array([len(p) for p in per])
+    for ch in range(4):
+        # pooled over instances (equal weights: every instance has 1042 ids)
+        p_g = xs[:, 7 + ch].mean()
+        p_o = (ref["P"][:, ch] * m).sum() / m.sum()
+        se = math.sqrt(max(p_g * (1 - p_g), 1e-12) / n + max(p_o * (1 - p_o), 1e-12) / m.sum())
+        assert abs(p_g - p_o) <= 3 * se, (ch, p_g, p_o, se)
+        for k in range(len(wl.instances)):
+            ng = xs[k, 0]
+            pg = min(max(xs[k, 7 + ch], 0.5 / ng), 1.0 - 0.5 / ng)
+            ko = int(round(ref["P"][k, ch] * m[k]))
+            pv = stats.binomtest(ko, int(m[k]), pg).pvalue
+            assert pv > 1e-4, (ch, k, xs[k, 7 + ch], ko, int(m[k]), pv)
+    print("pooled P gpu", xs[:, 7:11].mean(axis=0), "oracle subsample",
+          (ref["P"] * m[:, None]).sum(axis=0) / m.sum())
