@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 # hardware FP64 instruction counters on a full-wave fixed-step run of the
 # one-lane propagation kernel, per surface and RK variant.
 F_STEP = {("morse", 0): 1969.4, ("morse", 1): 4342.4,
-          ("mixed", 0): 1881.7, ("mixed", 1): 4194.7}
+          ("mixed", 0): 1821.7, ("mixed", 1): 4074.7}
 # HBM bytes per launch of the persistent kernel from FETCH_SIZE and WRITE_SIZE
 # passes scaled by a streaming kernel of known size, for the kernel as it was
 # when the counters were taken (workload, kernel) -> bytes; null otherwise.

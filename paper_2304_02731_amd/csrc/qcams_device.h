@@ -177,11 +177,29 @@ QD void pot_morse(const Pot& P, double r, double& V, double& d1, double& d2)
     d2 = 2.0 * De * a * a * e * (2.0 * e - 1.0);
 }
 
+// Cn r^-n and Cm r^-m of the generalized LJ pair from ir = 1/r.  The 12-6
+// form takes four multiplications; other exponents use binary powers, the
+// power of m serving for n = 2m.
+QD void lj_terms(const Pot& P, double ir, double& tn, double& tm)
+{
+    double pm, pn;
+    if (P.n == 12 && P.m == 6) {
+        const double i2 = ir * ir, i4 = i2 * i2;
+        pm = i4 * i2;
+        pn = pm * pm;
+    } else {
+        pm = ipow(ir, P.m);
+        pn = P.n == 2 * P.m ? pm * pm : ipow(ir, P.n);
+    }
+    tn = P.p0 * pn;
+    tm = P.p1 * pm;
+}
+
 QD void pot_lj(const Pot& P, double r, double& V, double& d1, double& d2)
 {
     const double ir = 1.0 / r;
-    const double tn = P.p0 * ipow(ir, P.n);   // Cn r^-n
-    const double tm = P.p1 * ipow(ir, P.m);   // Cm r^-m
+    double tn, tm;                            // Cn r^-n, Cm r^-m
+    lj_terms(P, ir, tn, tm);
     V = tn - tm;
     d1 = (-P.n * tn + P.m * tm) * ir;
     d2 = ((P.n * (P.n + 1.0)) * tn - (P.m * (P.m + 1.0)) * tm) * ir * ir;
@@ -221,7 +239,8 @@ QD double dV_over_r(const Pot& P, double r, double ir)
         const double e = exp_cw(P.p2 * (P.p1 - r));
         return (2.0 * P.p0 * P.p2) * (e - e * e) * ir;
     } else if (kind == LJ) {
-        const double tn = P.p0 * ipow(ir, P.n), tm = P.p1 * ipow(ir, P.m);
+        double tn, tm;
+        lj_terms(P, ir, tn, tm);
         return (-P.n * tn + P.m * tm) * ir * ir;
     } else {
         const double ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
