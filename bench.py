@@ -37,7 +37,7 @@ F_STEP = {("morse", 0): 1969.4, ("morse", 1): 4342.4,
 # when the counters were taken (workload, kernel) -> bytes; null otherwise.
 TRAFFIC = {("batched", "k_persistent<4,0,0,0,1>"): 136.50e6}
 RK_NAMES = {"dopri5": 0, "dop853": 1}
-KINDS = {"morse": "0,0,0", "mixed": "1,0,2"}
+KINDS = {"morse": "0,0,0", "mixed": "3,0,2"}   # 3: LJ 12-6 specialisation
 # workload -> (surface, default CPU-baseline stride)
 WORKLOADS = {"batched": ("morse", 25), "small": ("morse", 1), "mixed": ("mixed", 500),
              "sweep": ("morse", 5000)}

@@ -38,6 +38,7 @@ struct qcams_ctx {
     int64_t order_cap = 0;
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
     qcams_run_opts last_opts{};                   // effective options of the last run
+    bool lj126 = false;                           // pair AB is LJ 12-6
     bool has_run = false;
     // importance-sampling proposal (cells of b^2, chi, cos theta)
     double* d_prop_q = nullptr;
@@ -244,6 +245,14 @@ __global__ void k_run_tables(const Inst* inst, int n_inst, const int32_t* ord_in
     ids[pos] = inst[k].first_id + local;
 }
 
+// Makes a wave-uniform value opaque to the optimiser at this point, so that
+// what is computed from it stays where it is written.
+template <class T>
+__device__ inline void opaque_sgpr(T& v)
+{
+    asm volatile("" : "+s"(v));
+}
+
 // A trajectory's slot is one lane (W = 1) or a quad of lanes (W = 4, see the
 // lane layouts of the device header); the idle-slot count and a slot's rank
 // among the idle slots are the lane counts divided by W.
@@ -317,13 +326,19 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
             if (!active) {
                 const int64_t w = (int64_t)base + __popcll(idle & lt_mask) / W;
                 if (w < M.N) {
+                    // row addresses formed here, not hoisted out of the loop
+                    // (they would hold scalar registers across the steps)
+                    const double* dr = d;
+                    int64_t l = ld;
+                    opaque_sgpr(dr);
+                    opaque_sgpr(l);
                     pos = M.order[w];
-                    load_traj<W>(d, ld, pos, c, L);
-                    L.t = d[QCAMS_F_T * ld + pos];
-                    L.tmax = d[QCAMS_F_TMAX * ld + pos];
-                    const double rs = d[QCAMS_F_RSTOP * ld + pos];
+                    load_traj<W>(dr, l, pos, c, L);
+                    L.t = dr[QCAMS_F_T * l + pos];
+                    L.tmax = dr[QCAMS_F_TMAX * l + pos];
+                    const double rs = dr[QCAMS_F_RSTOP * l + pos];
                     L.rstop2 = rs * rs;
-                    L.h = d[QCAMS_F_H * ld + pos];
+                    L.h = dr[QCAMS_F_H * l + pos];
                     L.nstep = nstep[pos];
                     L.nrej = nrej[pos];
                     L.last_rej = 0;
@@ -346,10 +361,14 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
         }
         // ---- retire finished trajectories ----
         if (active && L.status != RUNNING) {
-            store_traj<W>(d, ld, pos, c, L);
+            double* dw = d;
+            int64_t l = ld;
+            opaque_sgpr(dw);
+            opaque_sgpr(l);
+            store_traj<W>(dw, l, pos, c, L);
             if (c == 0) {
-                d[QCAMS_F_T * ld + pos] = L.t;
-                d[QCAMS_F_H * ld + pos] = L.h;
+                dw[QCAMS_F_T * l + pos] = L.t;
+                dw[QCAMS_F_H * l + pos] = L.h;
                 nstep[pos] = L.nstep;
                 nrej[pos] = L.nrej;
                 status[pos] = (uint8_t)L.status;
@@ -620,14 +639,15 @@ static bool pair_ok(const qcams_pair& p)
 
 static bool pot_is_zero(const qcams_pair& p) { return p.kind == QCAMS_MORSE && p.p[0] == 0.0; }
 
-// Kernels are specialised for the all-Morse and the LJ/Morse/Buckingham pair
-// triples (other triples select the pair kind at run time) and for the RK
-// variant; `with_kinds` maps the context to the instantiation.
+// Kernels are specialised for the all-Morse and the LJ 12-6 / Morse /
+// Buckingham pair triples (other triples select the pair kind at run time)
+// and for the RK variant; `with_kinds` maps the context to the instantiation.
 template <template <int, int, int, int> class L, int RK, class... A>
 static void with_kinds(const qcams_ctx* c, A&&... a)
 {
     if (c->kinds == 0) L<0, 0, 0, RK>::go(a...);
-    else if (c->kinds == QCAMS_LJ + 3 * QCAMS_MORSE + 9 * QCAMS_BUCK) L<1, 0, 2, RK>::go(a...);
+    else if (c->kinds == QCAMS_LJ + 3 * QCAMS_MORSE + 9 * QCAMS_BUCK && c->lj126)
+        L<LJ126, 0, 2, RK>::go(a...);
     else L<-1, -1, -1, RK>::go(a...);
 }
 
@@ -773,6 +793,7 @@ int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qca
     int kk[3];
     for (int i = 0; i < 3; ++i) kk[i] = sys->pair[i].kind;
     c->kinds = kk[0] + 3 * kk[1] + 9 * kk[2];
+    c->lj126 = S.pot[0].kind == QCAMS_LJ && S.pot[0].n == 12 && S.pot[0].m == 6;
     c->prm.R0 = prm->R0;
     c->prm.t_stop = prm->t_stop;
     c->prm.r_stop = prm->r_stop;

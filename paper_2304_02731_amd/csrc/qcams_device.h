@@ -32,6 +32,8 @@ constexpr int kNQ = 48;          // midpoint nodes of the radial quadrature
 constexpr double kRFar = 1.0e5;  // outermost radius searched for a barrier (a0)
 
 enum Kind { MORSE = 0, LJ = 1, BUCK = 2 };
+// kernel specialisation code (never a pair's own kind): LJ with n = 12, m = 6
+constexpr int LJ126 = 3;
 enum Status { RUNNING = 0, OK_RSTOP = 1, OK_TMAX = 2, FAIL_MAXSTEPS = 3,
               FAIL_NONFINITE = 4, FAIL_HMIN = 5, COLLAPSE = 6 };
 enum Label { QUENCH = 0, R1 = 1, R2 = 2, DISS = 3, UNRESOLVED = 4, FAILED = 5 };
@@ -234,12 +236,20 @@ QD double pot_V(const Pot& P, double r)
 template <int K>
 QD double dV_over_r(const Pot& P, double r, double ir)
 {
-    const int kind = K >= 0 ? K : P.kind;
+    const int kind = K >= 0 ? (K == LJ126 ? LJ : K) : P.kind;
     if (kind == MORSE) {
         const double e = exp_cw(P.p2 * (P.p1 - r));
         return (2.0 * P.p0 * P.p2) * (e - e * e) * ir;
     } else if (kind == LJ) {
         double tn, tm;
+        if (K == LJ126) {
+            // the 12-6 branch of lj_terms, without the run-time test
+            const double i2 = ir * ir, i4 = i2 * i2;
+            const double pm = i4 * i2;
+            tn = P.p0 * (pm * pm);
+            tm = P.p1 * pm;
+            return (-12.0 * tn + 6.0 * tm) * ir * ir;
+        }
         lj_terms(P, ir, tn, tm);
         return (-P.n * tn + P.m * tm) * ir * ir;
     } else {
@@ -365,9 +375,19 @@ QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double*
         const double s = R.c == 1 ? sbc : (R.c == 2 ? sca : sab);
         double d, id;
         sqrt_rsqrt(s, d, id);
-        // one kind for all pairs: specialised; otherwise the lane's own kind
-        constexpr int KU = (K0 >= 0 && K0 == K1 && K1 == K2) ? K0 : -1;
-        const double g = dV_over_r<KU>(R.pot, d, id);
+        // one kind for all pairs: one specialised path; a specialised triple
+        // of kinds: each lane takes its pair's path (the wave runs all
+        // three); otherwise the lane's own kind at run time
+        double g;
+        if constexpr (K0 >= 0 && K0 == K1 && K1 == K2) {
+            g = dV_over_r<K0>(R.pot, d, id);
+        } else if constexpr (K0 >= 0 && K1 >= 0 && K2 >= 0) {
+            if (R.c == 1) g = dV_over_r<K1>(R.pot, d, id);
+            else if (R.c == 2) g = dV_over_r<K2>(R.pot, d, id);
+            else g = dV_over_r<K0>(R.pot, d, id);
+        } else {
+            g = dV_over_r<-1>(R.pot, d, id);
+        }
         gab = quad_perm<Bc<0>::ctrl>(g);
         gbc = quad_perm<Bc<1>::ctrl>(g);
         gca = quad_perm<Bc<2>::ctrl>(g);
