@@ -193,6 +193,25 @@ def config_paper_grid(n_per_b: int = 10_000) -> Workload:
     return Workload("h2ca_paper_grid_v1j0", h2ca_system(), Params(), out)
 
 
+# Integration tolerances (atol, rtol): the example values of Sec. 3.1 and the
+# timing-study values of Sec. 3.4 (Fig. 5).  A run uses the example values
+# where its integrator keeps every trajectory of the workload inside the
+# |dE/E| < 1e-8 energy gate, and the timing-study values otherwise.  Measured
+# on the listed workloads (largest |dE/E| over all trajectories): DOP853 on
+# the batched workload 3.6e-9 at the example values; DOPRI5 on it 2.7e-8
+# (fails), DOP853 on the sweep 1.1e-7 (fails), DOP853 on the mixed surface
+# 9.2e-9 (kept out: too close to the gate).
+TOL_EXAMPLE = (1.0e-10, 1.0e-11)
+TOL_TIMING = (1.0e-11, 1.0e-12)
+EXAMPLE_TOL_KEEPS_GATE = {("h2ca_batched_96inst_1e5", RK_DOP853)}
+
+
+def gated_params(wl: "Workload", rk: int) -> Params:
+    """The workload's parameters with RK variant rk and the tolerances above."""
+    atol, rtol = TOL_EXAMPLE if (wl.name, rk) in EXAMPLE_TOL_KEEPS_GATE else TOL_TIMING
+    return dataclasses.replace(wl.params, rk=rk, atol=atol, rtol=rtol)
+
+
 CONFIGS = {
     "small": config_small,
     "batched": config_batched,
