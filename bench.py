@@ -40,7 +40,7 @@ RK_NAMES = {"dopri5": 0, "dop853": 1}
 KINDS = {"morse": "0,0,0", "mixed": "3,0,2"}   # 3: LJ 12-6 specialisation
 # workload -> (surface, default CPU-baseline stride)
 WORKLOADS = {"batched": ("morse", 4), "small": ("morse", 1), "mixed": ("mixed", 500),
-             "sweep": ("morse", 5000)}
+             "sweep": ("morse", 5000), "paper_grid": ("morse", 1000)}
 PEAK_FP64_VECTOR = 78.6e12   # MI355X, FLOP/s
 
 
@@ -141,12 +141,16 @@ def main():
     n = ids.numel()
     st, out = buf["state"], buf["outcome"]
     prop_times = []
+    grid_groups = ctx.grid_groups()[0]
+    grid_out = []
 
     def step(timed):
         # units and levels of every instance (a1, a2), then the path (a3-a9)
         ctx.set_instances(wl.instances)
         if args.path == "run":
             ctx.run(buf, opts, stream=stream)
+            if grid_groups:
+                grid_out.append(ctx.grid_cross_sections(buf["xs"], stream=stream))
         else:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -230,6 +234,12 @@ def main():
         "wall_s": wall,
     }
     res["roofline"]["traffic"] = TRAFFIC.get((args.workload, res["roofline"]["kernel"]))
+    if grid_out:
+        g = grid_out[-1].cpu().numpy()
+        res["grid"] = {"E_c_K": g[:, Q.G_EC].tolist(),
+                       "sigma_a0^2 [q, r1, r2, d]": g[:, Q.G_SIGMA:Q.G_SIGMA + 4].tolist(),
+                       "sigma_err": g[:, Q.G_DSIGMA:Q.G_DSIGMA + 4].tolist(),
+                       "rate_au [q, r1, r2, d]": g[:, Q.G_RATE:Q.G_RATE + 4].tolist()}
     if args.learned:
         res["learned"] = learned_metric(args)
     if not args.no_cpu_baseline:

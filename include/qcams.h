@@ -162,6 +162,11 @@ typedef struct {
  *   sigma = 2 pi int P b db of Eq. (18): pi bmax^2 P for area sampling; NaN
  *   for fixed-b instances (combine those with a b grid). */
 #define QCAMS_XS_STRIDE 32
+/* Per-group results of fixed impact-parameter grids, rows of
+ * QCAMS_GRID_STRIDE doubles: [0] E_c (K), [1] v, [2] j, [3] number of b
+ * values, [4] largest b, [5] trajectories, [6..9] sigma_x, [10..13] its
+ * error, [14..17] rate k_x, for x = q, r1, r2, d; the rest 0. */
+#define QCAMS_GRID_STRIDE 24
 /* Gaussian-binning histograms, [n_inst][3][QCAMS_VMAX]: channel q, r1, r2 by
  * v_t, sum of w * W (Eq. (14) numerators). */
 #define QCAMS_VMAX 64
@@ -210,6 +215,16 @@ int qcams_init_conditions(qcams_ctx *ctx, const int64_t *ids, int64_t n,
  * untouched.  async. */
 int qcams_propagate(qcams_ctx *ctx, const qcams_state *st, int64_t n, void *stream);
 
+/* qcams_propagate with a record of each trajectory's pair distances (the
+ * quantities of the paper's trajectory plots, Sec. 2.2): the same steps as
+ * qcams_propagate, and (t, r_AB, r_BC, r_CA) at the start and after every
+ * accepted step written to rec (device [n][rec_max][4], trajectory-major),
+ * the number of points written to rec_n (device int32 [n]; 0 for a
+ * trajectory that was already stopped).  Past rec_max points a trajectory
+ * continues unrecorded.  async.  Errors: EINVAL. */
+int qcams_propagate_record(qcams_ctx *ctx, const qcams_state *st, int64_t n, double *rec,
+                           int32_t rec_max, int32_t *rec_n, void *stream);
+
 /* Product analysis (Sec. 2.2, Eq. (8)-(11)) of the final states 0..n-1.
  * async. */
 int qcams_classify(qcams_ctx *ctx, const qcams_state *st, int64_t n, const qcams_outcome *out,
@@ -224,6 +239,23 @@ int qcams_classify(qcams_ctx *ctx, const qcams_state *st, int64_t n, const qcams
 int qcams_cross_sections(qcams_ctx *ctx, const qcams_outcome *out, const int64_t *ids,
                          const double *weight, int64_t n, double *xs, double *hist,
                          void *stream);
+
+/* Fixed impact-parameter grids (the paper's Sec. 4 workflow): the installed
+ * QCAMS_B_FIXED instances form groups of equal (E_c, v, j), each ordered by
+ * b.  Number of groups, and (group_of, host [n_inst], may be NULL) the group
+ * of every instance (-1 for other sampling modes).  host only.  Errors:
+ * EINVAL. */
+int qcams_grid_groups(qcams_ctx *ctx, int32_t *n_groups, int32_t *group_of);
+
+/* Eq. (18)-(19) on every group: sigma_x = 2 pi int P_x(b) b db by the
+ * trapezoid rule over the group's b values (reading: prefactor 2 pi, P a
+ * probability; the integral runs from the smallest to the largest b), its
+ * error from the independent per-b errors of xs, and the rate
+ * k_x = sigma_x sqrt(2 E_c / mu_123).  xs: device [n_inst][QCAMS_XS_STRIDE]
+ * as written by qcams_cross_sections or qcams_run; out: device
+ * [n_groups][QCAMS_GRID_STRIDE].  No groups: nothing is written.  async.
+ * Errors: EINVAL. */
+int qcams_grid_cross_sections(qcams_ctx *ctx, const double *xs, double *out, void *stream);
 
 /* Options of the fused persistent run. */
 typedef struct {
@@ -284,8 +316,13 @@ int qcams_last_run_options(qcams_ctx *ctx, qcams_run_opts *used);
  * escale over non-failed trajectories is below energy_gate (<= 0: no gate)
  * is kept (best->rk = 1 or 2); the variant changes per-trajectory results,
  * the schedule does not.  With search_rk = 0 the context's variant is used
- * (best->rk = 0).  sync.  Errors as qcams_run; EINVAL also when no variant
- * keeps the gate. */
+ * (best->rk = 0).  Results are cached for the process, keyed by device,
+ * pair kinds, tolerances, RK variant, search_rk / energy_gate and the
+ * number of installed trajectories and instances: with reps >= 0 a cached
+ * result is returned without timing (reps = 0 counts as 1 otherwise); with
+ * reps < 0 the search runs with |reps| repetitions and replaces the cached
+ * result.  sync.  Errors as qcams_run; EINVAL also when no variant keeps
+ * the gate. */
 int qcams_autotune(qcams_ctx *ctx, const qcams_state *st, const qcams_outcome *out, int64_t *ids,
                    double *xs, int32_t reps, int32_t search_rk, double energy_gate,
                    qcams_run_opts *best, double *best_ms);

@@ -11,6 +11,9 @@
 #include <new>
 #include <algorithm>
 #include <functional>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/qcams.h"
@@ -27,6 +30,11 @@ struct qcams_ctx {
     int32_t n_inst = 0;
     int32_t inst_cap = 0;        // capacity of the device instance tables
     std::vector<Inst> h_inst;
+    // fixed-b grids: instances grouped by (E_c, v, j), sorted by b
+    int32_t* d_grid_inst = nullptr;   // [n_fixed] instance indices, group by group
+    int32_t* d_grid_off = nullptr;    // [n_groups + 1]
+    int32_t n_groups = 0, grid_cap = 0;
+    std::vector<int32_t> h_group_of;  // [n_inst] group of each instance, -1 if none
     int64_t n_total = 0;          // sum of n_traj
     int32_t* d_id_inst = nullptr;    // [n_inst] identity order
     // longest-expected-first order of the instances for the persistent run
@@ -203,6 +211,85 @@ __global__ void __launch_bounds__(256) k_propagate(Sys S, Prm P, double* d, int3
     nstep[i] = L.nstep;
     nrej[i] = L.nrej;
     status[i] = (uint8_t)L.status;
+}
+
+// ---------------------------------------------------------------------------
+// propagation with a record of the pair distances: the same steps as
+// k_propagate (one lane per trajectory, the same step function, so the same
+// trajectory), writing (t, r_AB, r_BC, r_CA) at the start and after every
+// accepted step into rec[i][0..rec_max), and the number written into rec_n.
+// Past rec_max points the trajectory continues unrecorded.
+// ---------------------------------------------------------------------------
+__device__ inline void record_point(const Sys& S, const Lane& L, double* r)
+{
+    double ab = 0.0, bc = 0.0, ca = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double x1 = L.x[a], x2 = L.x[3 + a];
+        const double u = x2 - S.cA * x1, w = -x2 - S.cB * x1;
+        ab += x1 * x1;
+        bc += u * u;
+        ca += w * w;
+    }
+    r[0] = L.t;
+    r[1] = sqrt(ab);
+    r[2] = sqrt(bc);
+    r[3] = sqrt(ca);
+}
+
+template <int K0, int K1, int K2, int RK>
+__global__ void __launch_bounds__(256) k_record(Sys S, Prm P, double* d, int32_t* nstep,
+                                                int32_t* nrej, uint8_t* status, int64_t ld,
+                                                int64_t n, double* rec, int32_t rec_max,
+                                                int32_t* rec_n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double* out = rec + i * (int64_t)rec_max * 4;
+    int32_t m = 0;
+    if (status[i] != RUNNING) {
+        rec_n[i] = 0;
+        return;
+    }
+    Lane L;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        L.x[f] = d[f * ld + i];
+        L.p[f] = d[(6 + f) * ld + i];
+    }
+    L.t = d[QCAMS_F_T * ld + i];
+    L.tmax = d[QCAMS_F_TMAX * ld + i];
+    const double rs = d[QCAMS_F_RSTOP * ld + i];
+    L.rstop2 = rs * rs;
+    L.h = d[QCAMS_F_H * ld + i];
+    L.nstep = nstep[i];
+    L.nrej = nrej[i];
+    L.status = RUNNING;
+    L.last_rej = 0;
+    double s2[3];
+    force<K0, K1, K2>(S, L.x, L.F, s2);
+    if (P.fixed_step) L.h = P.h_fixed;
+    else if (!(L.h > 0.0))
+        L.h = initial_step<K0, K1, K2, RK>(S, L.x, L.p, L.F, P.atol, P.rtol, L.tmax - L.t);
+    if (!is_finite(L.t) || !is_finite(L.tmax) || !is_finite(L.h)) L.status = FAIL_NONFINITE;
+    else if (L.t >= L.tmax) L.status = OK_TMAX;
+    else if (L.nstep >= P.max_steps) L.status = FAIL_MAXSTEPS;
+    if (m < rec_max) record_point(S, L, out + 4 * m++);
+    while (L.status == RUNNING) {
+        const int32_t before = L.nstep;
+        lane_step<K0, K1, K2, RK>(S, P, L);
+        if (L.nstep != before && m < rec_max) record_point(S, L, out + 4 * m++);
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        d[f * ld + i] = L.x[f];
+        d[(6 + f) * ld + i] = L.p[f];
+    }
+    d[QCAMS_F_T * ld + i] = L.t;
+    d[QCAMS_F_H * ld + i] = L.h;
+    nstep[i] = L.nstep;
+    nrej[i] = L.nrej;
+    status[i] = (uint8_t)L.status;
+    rec_n[i] = m;
 }
 
 // ---------------------------------------------------------------------------
@@ -524,6 +611,52 @@ k_xsec(const Inst* inst, int n_inst, double mu123, const uint8_t* label, const i
 }
 
 // ---------------------------------------------------------------------------
+// Eq. (18)-(19) on fixed impact-parameter grids: per group of fixed-b
+// instances with the same (E_c, v, j), ordered by b, sigma_x = 2 pi int P_x b db
+// by the trapezoid rule over the grid (the reading 2 pi of the prefactor; b
+// from the first to the last grid point), its error from the independent
+// per-b errors, and the rate k_x = sigma_x sqrt(2 E_c / mu_123).  One thread
+// per group.
+// ---------------------------------------------------------------------------
+__global__ void k_grid_xs(const Inst* inst, const int32_t* gidx, const int32_t* goff, int n_groups,
+                          double mu123, const double* xs, double* out)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    const int b0 = goff[g], b1 = goff[g + 1];
+    double sig[4] = {0, 0, 0, 0}, var[4] = {0, 0, 0, 0}, N = 0.0;
+    for (int q = b0; q < b1; ++q) {
+        const int k = gidx[q];
+        const double b = inst[k].b;
+        const double lo = q > b0 ? inst[gidx[q - 1]].b : b;
+        const double hi = q + 1 < b1 ? inst[gidx[q + 1]].b : b;
+        const double w = 0.5 * (hi - lo);                // trapezoid weight of this node
+        const double* row = xs + (int64_t)k * QCAMS_XS_STRIDE;
+        N += row[0];
+        for (int c = 0; c < 4; ++c) {
+            const double f = w * (2.0 * kPi * b);
+            sig[c] += f * row[7 + c];
+            var[c] += (f * row[11 + c]) * (f * row[11 + c]);
+        }
+    }
+    const Inst& I = inst[gidx[b0]];
+    double* o = out + (int64_t)g * QCAMS_GRID_STRIDE;
+    o[0] = I.Ec_K;
+    o[1] = I.v;
+    o[2] = I.j;
+    o[3] = b1 - b0;
+    o[4] = inst[gidx[b1 - 1]].b;
+    o[5] = N;
+    const double speed = sqrt(2.0 * I.Ec / mu123);
+    for (int c = 0; c < 4; ++c) {
+        o[6 + c] = sig[c];
+        o[10 + c] = sqrt(var[c]);
+        o[14 + c] = sig[c] * speed;
+    }
+    for (int c = 18; c < QCAMS_GRID_STRIDE; ++c) o[c] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
 // learned proposal: network inputs, cell table, cumulative distribution
 // ---------------------------------------------------------------------------
 constexpr double kFeatB = 10.0;   // impact parameter scale of the input (a0)
@@ -664,6 +797,17 @@ struct PropagateL {
     {
         hipLaunchKernelGGL((k_propagate<K0, K1, K2, RK>), dim3(grid_of(n, 256)), dim3(256), 0, s,
                            c->sys, c->prm, st->d, st->nstep, st->nrej, st->status, st->ld, n);
+    }
+};
+
+template <int K0, int K1, int K2, int RK>
+struct RecordL {
+    static void go(qcams_ctx* c, const qcams_state* st, int64_t n, double* rec, int32_t rec_max,
+                   int32_t* rec_n, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_record<K0, K1, K2, RK>), dim3(grid_of(n, 64)), dim3(64), 0, s, c->sys,
+                           c->prm, st->d, st->nstep, st->nrej, st->status, st->ld, n, rec, rec_max,
+                           rec_n);
     }
 };
 
@@ -828,7 +972,8 @@ void qcams_destroy(qcams_ctx* c)
     if (c->d_order) (void)hipFree(c->d_order);
     for (int e = 0; e < 2; ++e)
         if (c->ev_prop[e]) (void)hipEventDestroy(c->ev_prop[e]);
-    for (void* q : {(void*)c->d_prop_q, (void*)c->d_prop_cdf, (void*)c->d_cell_x, (void*)c->d_cell_p})
+    for (void* q : {(void*)c->d_prop_q, (void*)c->d_prop_cdf, (void*)c->d_cell_x, (void*)c->d_cell_p,
+                    (void*)c->d_grid_inst, (void*)c->d_grid_off})
         if (q) (void)hipFree(q);
     delete c;
 }
@@ -888,6 +1033,7 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
             return fail(c, QCAMS_EINVAL, "instance %d: ids overlap or are not sorted", k);
         // kelvin -> hartree (Boltzmann constant in E_h / K, CODATA 2018)
         h[k].Ec = q.Ec_K * 3.1668115634556e-6;
+        h[k].Ec_K = q.Ec_K;
         h[k].b = q.b;
         h[k].bmax = q.bmax;
         h[k].b_mode = q.b_mode;
@@ -934,6 +1080,51 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
     HIP_OK(c, hipMemcpy(c->d_inst, h.data(), n_inst * sizeof(Inst), hipMemcpyHostToDevice));
     c->n_inst = n_inst;
     c->h_inst = h;
+    // fixed-b groups, keyed by (E_c, v, j) in order of first appearance
+    {
+        std::vector<std::vector<int32_t>> groups;
+        std::vector<std::tuple<double, int, int>> keys;
+        c->h_group_of.assign(n_inst, -1);
+        for (int k = 0; k < n_inst; ++k) {
+            if (inst[k].b_mode != QCAMS_B_FIXED) continue;
+            const auto key = std::make_tuple(inst[k].Ec_K, inst[k].v, inst[k].j);
+            int g = -1;
+            for (size_t q = 0; q < keys.size(); ++q)
+                if (keys[q] == key) { g = (int)q; break; }
+            if (g < 0) {
+                g = (int)keys.size();
+                keys.push_back(key);
+                groups.emplace_back();
+            }
+            groups[g].push_back(k);
+            c->h_group_of[k] = g;
+        }
+        std::vector<int32_t> gidx, goff(1, 0);
+        for (auto& m : groups) {
+            std::stable_sort(m.begin(), m.end(),
+                             [&](int32_t a, int32_t b) { return inst[a].b < inst[b].b; });
+            gidx.insert(gidx.end(), m.begin(), m.end());
+            goff.push_back((int32_t)gidx.size());
+        }
+        const int ng = (int)groups.size();
+        if (ng > 0 && (int)gidx.size() + ng + 1 > c->grid_cap) {
+            if (c->d_grid_inst) HIP_OK(c, hipFree(c->d_grid_inst));
+            if (c->d_grid_off) HIP_OK(c, hipFree(c->d_grid_off));
+            c->d_grid_inst = c->d_grid_off = nullptr;
+            c->grid_cap = 0;
+            if (hipMalloc(&c->d_grid_inst, gidx.size() * sizeof(int32_t)) != hipSuccess ||
+                hipMalloc(&c->d_grid_off, (ng + 1) * sizeof(int32_t)) != hipSuccess)
+                return fail(c, QCAMS_ENOMEM, "grid table allocation failed");
+            c->grid_cap = (int)gidx.size() + ng + 1;
+        }
+        if (ng > 0) {
+            HIP_OK(c, hipMemcpy(c->d_grid_inst, gidx.data(), gidx.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice));
+            HIP_OK(c, hipMemcpy(c->d_grid_off, goff.data(), goff.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice));
+        }
+        c->n_groups = ng;
+    }
     // natural offsets and the longest-expected-first order: expected trial
     // steps of a trajectory ~ collision time / vibrational period ~ 1/(v_c tau)
     std::vector<int64_t> nat(n_inst + 1, 0), loff(n_inst + 1, 0);
@@ -988,6 +1179,20 @@ int qcams_propagate(qcams_ctx* c, const qcams_state* st, int64_t n, void* stream
     HIP_OK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     with_variant<PropagateL>(c, c->prm.rk, c, st, n, s);
+    HIP_OK(c, hipGetLastError());
+    return QCAMS_OK;
+}
+
+int qcams_propagate_record(qcams_ctx* c, const qcams_state* st, int64_t n, double* rec,
+                           int32_t rec_max, int32_t* rec_n, void* stream)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    if (int rc = check_state(c, st, n)) return rc;
+    if (rec_max < 1 || (n > 0 && (!rec || !rec_n)))
+        return fail(c, QCAMS_EINVAL, "record buffers missing or rec_max < 1");
+    if (n == 0) return QCAMS_OK;
+    HIP_OK(c, hipSetDevice(c->device));
+    with_variant<RecordL>(c, c->prm.rk, c, st, n, rec, rec_max, rec_n, (hipStream_t)stream);
     HIP_OK(c, hipGetLastError());
     return QCAMS_OK;
 }
@@ -1232,6 +1437,32 @@ static int tune_energy(qcams_ctx* c, const qcams_outcome* out, double* worst)
     return QCAMS_OK;
 }
 
+// Autotune results of this process, keyed by what decides them: the device,
+// the kernel specialisation, the tolerances and RK variant, the variant
+// search and its gate, and the size of the installed work.
+struct TuneKey {
+    int device, kinds, lj126, search_rk, rk;
+    double atol, rtol, gate;
+    int64_t n_total;
+    int32_t n_inst;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(device, kinds, lj126, search_rk, rk, atol, rtol, gate, n_total, n_inst) <
+               std::tie(o.device, o.kinds, o.lj126, o.search_rk, o.rk, o.atol, o.rtol, o.gate,
+                        o.n_total, o.n_inst);
+    }
+};
+struct TuneVal {
+    qcams_run_opts opts;
+    double ms;
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneVal> g_tune;
+
+static int autotune_search(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out,
+                           int64_t* ids, double* xs, int32_t reps, int32_t search_rk,
+                           double energy_gate, qcams_run_opts* best, double* best_ms);
+
 int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out, int64_t* ids,
                    double* xs, int32_t reps, int32_t search_rk, double energy_gate,
                    qcams_run_opts* best, double* best_ms)
@@ -1239,7 +1470,34 @@ int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out
     if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
     if (!best) return fail(c, QCAMS_EINVAL, "null result");
     if (search_rk != 0 && search_rk != 1) return fail(c, QCAMS_EINVAL, "search_rk must be 0 or 1");
-    if (reps < 1) reps = 1;
+    const TuneKey key{c->device, c->kinds, c->lj126 ? 1 : 0, search_rk, c->prm.rk,
+                      c->prm.atol, c->prm.rtol, search_rk ? energy_gate : 0.0, c->n_total,
+                      c->n_inst};
+    if (reps >= 0) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *best = it->second.opts;
+            if (best_ms) *best_ms = it->second.ms;
+            return QCAMS_OK;
+        }
+    }
+    double ms = 0.0;
+    const int rc = autotune_search(c, st, out, ids, xs, reps < 0 ? -reps : (reps < 1 ? 1 : reps),
+                                   search_rk, energy_gate, best, &ms);
+    if (rc != QCAMS_OK) return rc;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[key] = TuneVal{*best, ms};
+    }
+    if (best_ms) *best_ms = ms;
+    return QCAMS_OK;
+}
+
+static int autotune_search(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out,
+                           int64_t* ids, double* xs, int32_t reps, int32_t search_rk,
+                           double energy_gate, qcams_run_opts* best, double* best_ms)
+{
     HIP_OK(c, hipSetDevice(c->device));
     hipStream_t s = nullptr;
     HIP_OK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -1323,6 +1581,29 @@ int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out
     if (rc != QCAMS_OK) return rc == QCAMS_EHIP ? fail(c, rc, "autotune run failed") : rc;
     *best = bo;
     if (best_ms) *best_ms = best_t;
+    return QCAMS_OK;
+}
+
+int qcams_grid_groups(qcams_ctx* c, int32_t* n_groups, int32_t* group_of)
+{
+    if (!c || !n_groups) return fail(c, QCAMS_EINVAL, "null argument");
+    if (c->n_inst < 1) return fail(c, QCAMS_EINVAL, "no instances installed");
+    *n_groups = c->n_groups;
+    if (group_of)
+        for (int k = 0; k < c->n_inst; ++k) group_of[k] = c->h_group_of[k];
+    return QCAMS_OK;
+}
+
+int qcams_grid_cross_sections(qcams_ctx* c, const double* xs, double* out, void* stream)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    if (c->n_inst < 1) return fail(c, QCAMS_EINVAL, "no instances installed");
+    if (c->n_groups == 0) return QCAMS_OK;
+    if (!xs || !out) return fail(c, QCAMS_EINVAL, "null buffer");
+    HIP_OK(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_grid_xs, dim3(grid_of(c->n_groups, 64)), dim3(64), 0, (hipStream_t)stream,
+                       c->d_inst, c->d_grid_inst, c->d_grid_off, c->n_groups, c->sys.mu123, xs, out);
+    HIP_OK(c, hipGetLastError());
     return QCAMS_OK;
 }
 

@@ -81,6 +81,7 @@ struct Inst {
     int64_t n_traj, first_id;
     uint64_t seed;
     double Evj, rminus, rplus, tau;
+    double Ec_K;        // collision energy as given, kelvin
 };
 
 // ---------------------------------------------------------------------------

@@ -28,11 +28,13 @@ RK_DOPRI5, RK_DOP853 = 0, 1
 MLP_NPARAM, MLP_NIN, MLP_NOUT, PROP_CELLS = 34436, 6, 4, 8192
 RUNNING, OK_RSTOP, OK_TMAX, FAIL_MAXSTEPS, FAIL_NONFINITE, FAIL_HMIN, COLLAPSE = range(7)
 QUENCH, R1, R2, DISS, UNRESOLVED, FAILED = range(6)
-NF, NS, XS_STRIDE, VMAX = 18, 6, 32, 64
+NF, NS, XS_STRIDE, VMAX, GRID_STRIDE = 18, 6, 32, 64, 24
 F_X, F_P, F_T, F_TMAX, F_RSTOP, F_E0, F_ESCALE, F_H = 0, 6, 12, 13, 14, 15, 16, 17
 # columns of a cross-section row
 XS_N, XS_COUNTS, XS_P, XS_DP, XS_SIGMA, XS_DSIGMA, XS_RATE, XS_WTOT, XS_SUMW, XS_SUMW2 = \
     0, 1, 7, 11, 15, 19, 23, 27, 28, 29
+# columns of a fixed-b grid row
+G_EC, G_V, G_J, G_NB, G_BMAX, G_N, G_SIGMA, G_DSIGMA, G_RATE = 0, 1, 2, 3, 4, 5, 6, 10, 14
 
 # unit conversions of the binding (CODATA 2018)
 AMU_IN_ME = 1822.888486209
@@ -120,6 +122,9 @@ def lib():
                             vp, vp, vp, vp]
     L.qcams_last_run_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
     L.qcams_last_run_options.argtypes = [vp, C.POINTER(RunOpts)]
+    L.qcams_grid_groups.argtypes = [vp, C.POINTER(C.c_int32), vp]
+    L.qcams_propagate_record.argtypes = [vp, C.POINTER(StateC), i64, vp, i32, vp, vp]
+    L.qcams_grid_cross_sections.argtypes = [vp, vp, vp, vp]
     L.qcams_autotune.argtypes = [vp, C.POINTER(StateC), C.POINTER(OutcomeC), vp, vp, i32, i32,
                                  C.c_double, C.POINTER(RunOpts), C.POINTER(C.c_double)]
     L.qcams_mlp_create.argtypes = [C.POINTER(vp), C.c_int, vp, C.c_uint64]
@@ -368,15 +373,49 @@ class Context:
         self._check(lib().qcams_last_run_kernel_ms(self._h, C.byref(ms)), "qcams_last_run_kernel_ms")
         return ms.value
 
+    def propagate_record(self, st: State, rec_max: int, n: Optional[int] = None, stream=None):
+        """qcams_propagate recording (t, r_AB, r_BC, r_CA) after every accepted
+        step: returns (rec [n, rec_max, 4], counts [n]) device tensors."""
+        import torch
+        n = st.d.shape[1] if n is None else n
+        rec = torch.zeros((n, rec_max, 4), dtype=torch.float64, device=self.torch_device)
+        cnt = torch.zeros(n, dtype=torch.int32, device=self.torch_device)
+        self._check(lib().qcams_propagate_record(self._h, C.byref(st.c()), n, rec.data_ptr(),
+                                                 rec_max, cnt.data_ptr(), _stream(stream)),
+                    "qcams_propagate_record")
+        return rec, cnt
+
+    def grid_groups(self):
+        """(number of fixed-b groups, group index of every instance)."""
+        import numpy as np
+        ng = C.c_int32()
+        g = np.zeros(len(self.instances), dtype=np.int32)
+        self._check(lib().qcams_grid_groups(self._h, C.byref(ng), g.ctypes.data), "qcams_grid_groups")
+        return ng.value, g
+
+    def grid_cross_sections(self, xs, stream=None):
+        """Per-group sigma, error and rate on fixed-b grids (qcams_grid_cross_sections)."""
+        import torch
+        ng, _ = self.grid_groups()
+        out = torch.zeros((max(ng, 1), GRID_STRIDE), dtype=torch.float64, device=self.torch_device)
+        self._check(lib().qcams_grid_cross_sections(self._h, xs.data_ptr(), out.data_ptr(),
+                                                    _stream(stream)),
+                    "qcams_grid_cross_sections")
+        return out[:ng]
+
     def last_run_options(self) -> RunOpts:
         """Effective options of the last run (qcams_last_run_options)."""
         o = RunOpts()
         self._check(lib().qcams_last_run_options(self._h, C.byref(o)), "qcams_last_run_options")
         return o
 
-    def autotune(self, buf, reps: int = 1, search_rk: bool = False, energy_gate: float = 1e-8):
+    def autotune(self, buf, reps: int = 1, search_rk: bool = False, energy_gate: float = 1e-8,
+                 retune: bool = False):
         """Fastest qcams_run options on the installed instances (qcams_autotune);
-        with search_rk also the RK variant, among those keeping the energy gate."""
+        with search_rk also the RK variant, among those keeping the energy gate.
+        A result cached for the same key is returned unless retune is set."""
+        if retune:
+            reps = -max(1, reps)
         best = RunOpts()
         ms = C.c_double()
         self._check(lib().qcams_autotune(self._h, C.byref(buf["state"].c()),

@@ -191,6 +191,25 @@ def test_autotune_returns_valid_options(Q, torch, search_rk):
     print("autotuned", best.as_dict(), "%.2f ms" % ms)
 
 
+def test_autotune_cache(Q, torch):
+    """A second autotune of the same key returns the cached options and time
+    without timing again; retune replaces the entry."""
+    wl = _mixed_energy_workload(per=24)
+    ctx = Q.Context(wl.system, wl.params)
+    ctx.set_instances(wl.instances)
+    buf = ctx.new_run_buffers()
+    b1, ms1 = ctx.autotune(buf, reps=1)
+    ctx2 = Q.Context(wl.system, wl.params)          # another context, same key
+    ctx2.set_instances(wl.instances)
+    buf2 = ctx2.new_run_buffers()
+    b2, ms2 = ctx2.autotune(buf2, reps=1)
+    assert b1.as_dict() == b2.as_dict() and ms1 == ms2
+    b3, ms3 = ctx2.autotune(buf2, reps=1, retune=True)
+    assert ms3 != ms1 and b3.lanes in (1, 4)
+    b4, ms4 = ctx.autotune(buf, reps=1)
+    assert b4.as_dict() == b3.as_dict() and ms4 == ms3
+
+
 def test_variant_override_equals_context_variant(Q, torch):
     """RunOpts.rk = 2 on a DOPRI5 context equals a DOP853 context's run."""
     wl = _mixed_energy_workload(per=48)
