@@ -194,9 +194,28 @@ const char *qcams_last_error(const qcams_ctx *ctx);
  * EUNBOUND (some level is not bound; its row is NaN), EINVAL. */
 int qcams_levels(qcams_ctx *ctx, int32_t n, const int32_t *v, const int32_t *j, double *out);
 
+/* Levels of AB from the Colbert-Miller DVR, the paper's internal-energy
+ * method (Sec. 2.1; input keys npts, xmin, xmax of Sec. 3.1): E_vj is the
+ * (v+1)-th lowest eigenvalue of the radial Hamiltonian with the centrifugal
+ * term j(j+1)/(2 mu r^2) on the npts interior points of the box
+ * (xmin, xmax) (particle-in-a-box form; one dense eigenproblem per distinct
+ * j, reduced to tridiagonal form and bisected on the device); r-, r+ and
+ * tau at that energy as in qcams_levels.  out: host [n][4].  sync.
+ * Errors: EINVAL (grid: 16 <= npts <= 4096, 0 < xmin < xmax), EUNBOUND
+ * (E_vj above the well), ENOROOT, ENOMEM, EHIP. */
+int qcams_dvr_levels(qcams_ctx *ctx, int32_t npts, double xmin, double xmax, int32_t n,
+                     const int32_t *v, const int32_t *j, double *out);
+
+#define QCAMS_LEVELS_BS 0
+#define QCAMS_LEVELS_DVR 1
+/* Level method used by qcams_set_instances: QCAMS_LEVELS_BS (default,
+ * Bohr-Sommerfeld, qcams_levels) or QCAMS_LEVELS_DVR with its grid
+ * (qcams_dvr_levels).  host only.  Errors: EINVAL. */
+int qcams_set_level_method(qcams_ctx *ctx, int32_t method, int32_t npts, double xmin, double xmax);
+
 /* Install the instance table (host array of n_inst rows, sorted by
  * first_id, id ranges disjoint) and compute each instance's level on the
- * device.  sync.  Errors: EINVAL, EUNBOUND. */
+ * device with the context's level method.  sync.  Errors: EINVAL, EUNBOUND. */
 int qcams_set_instances(qcams_ctx *ctx, const qcams_instance *inst, int32_t n_inst);
 
 /* Initial conditions (Sec. 2.1, Eq. (5)-(6)) of trajectories ids[0..n)

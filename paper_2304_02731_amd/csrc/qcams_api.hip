@@ -47,6 +47,9 @@ struct qcams_ctx {
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
     qcams_run_opts last_opts{};                   // effective options of the last run
     bool lj126 = false;                           // pair AB is LJ 12-6
+    int level_method = QCAMS_LEVELS_BS;           // levels of qcams_set_instances
+    int dvr_npts = 0;
+    double dvr_xmin = 0.0, dvr_xmax = 0.0;
     bool has_run = false;
     // importance-sampling proposal (cells of b^2, chi, cos theta)
     double* d_prop_q = nullptr;
@@ -102,6 +105,18 @@ __global__ void k_levels(Pot P, Shape Sh, double mu, int n, const int* v, const 
     double o[4] = {NAN, NAN, NAN, NAN};
     rc[i] = bs_level(P, Sh, mu, v[i], j[i], o);
     if (rc[i] != 0) o[0] = o[1] = o[2] = o[3] = NAN;
+    for (int k = 0; k < 4; ++k) out[4 * i + k] = o[k];
+}
+
+// turning points and period at given energies (the DVR levels)
+__global__ void k_levels_at(Pot P, Shape Sh, double mu, int n, const double* E, const int* j,
+                            double* out, int* rc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double o[4] = {NAN, NAN, NAN, NAN};
+    rc[i] = level_at_energy(P, Sh, mu, j[i], E[i], o);
+    if (rc[i] != 0) o[1] = o[2] = o[3] = NAN;
     for (int k = 0; k < 4; ++k) out[4 * i + k] = o[k];
 }
 
@@ -1016,6 +1031,80 @@ int qcams_levels(qcams_ctx* c, int32_t n, const int32_t* v, const int32_t* j, do
     return QCAMS_OK;
 }
 
+int qd_dvr_eigenvalues(int device, const Pot& P, double mu, double a, double b, int n, int nj,
+                       const int* js, int K, double* out, char* err, size_t errlen);
+
+int qcams_dvr_levels(qcams_ctx* c, int32_t npts, double xmin, double xmax, int32_t n,
+                     const int32_t* v, const int32_t* j, double* out)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    if (n < 0 || (n > 0 && (!v || !j || !out))) return fail(c, QCAMS_EINVAL, "bad arguments");
+    if (npts < 16 || npts > 4096 || !(xmin > 0.0) || !(xmax > xmin))
+        return fail(c, QCAMS_EINVAL, "DVR grid: need 16 <= npts <= 4096 and 0 < xmin < xmax");
+    if (n == 0) return QCAMS_OK;
+    std::vector<int> js;
+    int K = 0;
+    for (int i = 0; i < n; ++i) {
+        if (v[i] < 0 || j[i] < 0) return fail(c, QCAMS_EINVAL, "negative quantum number");
+        if (v[i] >= npts) return fail(c, QCAMS_EUNBOUND, "v=%d exceeds the DVR grid", v[i]);
+        if (std::find(js.begin(), js.end(), j[i]) == js.end()) js.push_back(j[i]);
+        K = std::max(K, v[i] + 1);
+    }
+    std::vector<double> eig((size_t)K * js.size());
+    char msg[200] = {0};
+    const int drc = qd_dvr_eigenvalues(c->device, c->sys.pot[0], c->sys.mu12, xmin, xmax, npts,
+                                       (int)js.size(), js.data(), K, eig.data(), msg, sizeof msg);
+    if (drc == -1) return fail(c, QCAMS_ENOMEM, "%s", msg);
+    if (drc != 0) return fail(c, QCAMS_EHIP, "%s", msg);
+    std::vector<double> E(n);
+    for (int i = 0; i < n; ++i) {
+        const size_t q = std::find(js.begin(), js.end(), j[i]) - js.begin();
+        E[i] = eig[q * K + v[i]];
+    }
+    HIP_OK(c, hipSetDevice(c->device));
+    int *dj = nullptr, *drc2 = nullptr;
+    double *dE = nullptr, *dout = nullptr;
+    std::vector<int> rc(n);
+    hipError_t e = hipMalloc(&dj, n * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&drc2, n * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&dE, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&dout, 4 * (size_t)n * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(dj, j, n * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dE, E.data(), n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_levels_at, dim3(grid_of(n, 64)), dim3(64), 0, 0, c->sys.pot[0],
+                           c->sys.shape[0], c->sys.mu12, n, (const double*)dE, (const int*)dj, dout,
+                           drc2);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, dout, 4 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(rc.data(), drc2, n * sizeof(int), hipMemcpyDeviceToHost);
+    for (void* q : {(void*)dj, (void*)drc2, (void*)dE, (void*)dout}) (void)hipFree(q);
+    if (e != hipSuccess) return fail(c, QCAMS_EHIP, "DVR levels: %s", hipGetErrorString(e));
+    for (int i = 0; i < n; ++i) {
+        if (rc[i] == -2) return fail(c, QCAMS_EUNBOUND, "DVR level v=%d j=%d is not bound", v[i], j[i]);
+        if (rc[i] != 0) return fail(c, QCAMS_ENOROOT, "DVR level v=%d j=%d: no turning points", v[i], j[i]);
+    }
+    return QCAMS_OK;
+}
+
+int qcams_set_level_method(qcams_ctx* c, int32_t method, int32_t npts, double xmin, double xmax)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    if (method == QCAMS_LEVELS_BS) {
+        c->level_method = method;
+        return QCAMS_OK;
+    }
+    if (method != QCAMS_LEVELS_DVR) return fail(c, QCAMS_EINVAL, "unknown level method");
+    if (npts < 16 || npts > 4096 || !(xmin > 0.0) || !(xmax > xmin))
+        return fail(c, QCAMS_EINVAL, "DVR grid: need 16 <= npts <= 4096 and 0 < xmin < xmax");
+    c->level_method = method;
+    c->dvr_npts = npts;
+    c->dvr_xmin = xmin;
+    c->dvr_xmax = xmax;
+    return QCAMS_OK;
+}
+
 int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst)
 {
     if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
@@ -1046,7 +1135,10 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
         jj[k] = q.j;
     }
     std::vector<double> lev(4 * (size_t)n_inst);
-    int rc = qcams_levels(c, n_inst, vv.data(), jj.data(), lev.data());
+    int rc = c->level_method == QCAMS_LEVELS_DVR
+                 ? qcams_dvr_levels(c, c->dvr_npts, c->dvr_xmin, c->dvr_xmax, n_inst, vv.data(),
+                                    jj.data(), lev.data())
+                 : qcams_levels(c, n_inst, vv.data(), jj.data(), lev.data());
     if (rc != QCAMS_OK) return rc;
     for (int k = 0; k < n_inst; ++k) {
         h[k].Evj = lev[4 * k + 0];

@@ -513,7 +513,7 @@ constexpr Vals vals()
 }
 constexpr Vals VALS = vals();
 }  // namespace dp
-__constant__ dp::Vals kDp = dp::vals();
+static __constant__ dp::Vals kDp = dp::vals();
 
 QD kcoef_t* dp_coefs()
 {
@@ -707,7 +707,7 @@ constexpr Vals vals()
 }
 constexpr Vals VALS = vals();
 }  // namespace d8
-__constant__ d8::Vals kD8 = d8::vals();
+static __constant__ d8::Vals kD8 = d8::vals();
 
 QD kcoef_t* d8_coefs()
 {
@@ -1210,6 +1210,27 @@ QD int bs_level(const Pot& P, const Shape& Sh, double mu, int v, int j, double* 
         E = En;
         if (done) break;
     }
+    if (!turning_points(P, Sh, R, mu, J2, E, rm, rp)) return -3;
+    action_period(P, mu, J2, E, rm, rp, act, per);
+    out[0] = E;
+    out[1] = rm;
+    out[2] = rp;
+    out[3] = per;
+    return 0;
+}
+
+// Turning points and period of the AB pair at a given energy E of level
+// (v, j) (E from the DVR): out = E, r-, r+, tau.  Returns -2 when E is not
+// inside the well of V_eff.
+QD int level_at_energy(const Pot& P, const Shape& Sh, double mu, int j, double E, double* out)
+{
+    const double J2 = (double)j * (j + 1.0);
+    const Radial R = radial(P, Sh, mu, J2);
+    if (!R.well) return -2;
+    const double Elo = veff(P, mu, J2, R.rw);
+    const double Ehi = R.barrier ? veff(P, mu, J2, R.r0) : 0.0;
+    if (!(E > Elo && E < Ehi)) return -2;
+    double rm, rp, act, per;
     if (!turning_points(P, Sh, R, mu, J2, E, rm, rp)) return -3;
     action_period(P, mu, J2, E, rm, rp, act, per);
     out[0] = E;

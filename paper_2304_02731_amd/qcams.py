@@ -25,6 +25,7 @@ OK, EINVAL, EUNBOUND, ENOROOT, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
 MORSE, LJ, BUCK = 0, 1, 2
 B_FIXED, B_AREA, B_PROPOSAL = 0, 1, 2
 RK_DOPRI5, RK_DOP853 = 0, 1
+LEVELS_BS, LEVELS_DVR = 0, 1
 MLP_NPARAM, MLP_NIN, MLP_NOUT, PROP_CELLS = 34436, 6, 4, 8192
 RUNNING, OK_RSTOP, OK_TMAX, FAIL_MAXSTEPS, FAIL_NONFINITE, FAIL_HMIN, COLLAPSE = range(7)
 QUENCH, R1, R2, DISS, UNRESOLVED, FAILED = range(6)
@@ -123,6 +124,8 @@ def lib():
     L.qcams_last_run_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
     L.qcams_last_run_options.argtypes = [vp, C.POINTER(RunOpts)]
     L.qcams_grid_groups.argtypes = [vp, C.POINTER(C.c_int32), vp]
+    L.qcams_dvr_levels.argtypes = [vp, i32, C.c_double, C.c_double, i32, vp, vp, vp]
+    L.qcams_set_level_method.argtypes = [vp, i32, i32, C.c_double, C.c_double]
     L.qcams_propagate_record.argtypes = [vp, C.POINTER(StateC), i64, vp, i32, vp, vp]
     L.qcams_grid_cross_sections.argtypes = [vp, vp, vp, vp]
     L.qcams_autotune.argtypes = [vp, C.POINTER(StateC), C.POINTER(OutcomeC), vp, vp, i32, i32,
@@ -279,6 +282,22 @@ class Context:
             raise QcamsError("%s failed (%d): %s" % (what, rc, lib().qcams_last_error(self._h).decode()))
 
     # ---- synchronous set-up ----
+    def dvr_levels(self, npts: int, xmin: float, xmax: float, v: Sequence[int],
+                   j: Sequence[int]) -> np.ndarray:
+        """(E, r-, r+, tau) per (v, j) from the Colbert-Miller DVR (qcams_dvr_levels)."""
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        out = np.zeros((len(v), 4))
+        self._check(lib().qcams_dvr_levels(self._h, npts, xmin, xmax, len(v), v.ctypes.data,
+                                           j.ctypes.data, out.ctypes.data), "qcams_dvr_levels")
+        return out
+
+    def set_level_method(self, method: int, npts: int = 0, xmin: float = 0.0,
+                         xmax: float = 0.0):
+        """Levels of later set_instances calls: LEVELS_BS or LEVELS_DVR with a grid."""
+        self._check(lib().qcams_set_level_method(self._h, method, npts, xmin, xmax),
+                    "qcams_set_level_method")
+
     def levels(self, v: Sequence[int], j: Sequence[int]) -> np.ndarray:
         v = np.ascontiguousarray(v, dtype=np.int32)
         j = np.ascontiguousarray(j, dtype=np.int32)

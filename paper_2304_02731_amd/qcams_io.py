@@ -10,10 +10,10 @@ LJ {``m``, ``n``, ``cm``, ``cn``, ``re``}, Buckingham {``a``, ``b``, ``c6``,
 ``re``, ``max``}, and the DVR grid {``npts``, ``xmin``, ``xmax``}.  All in
 atomic units except the collision energy (kelvin).  The Morse range
 parameter follows from the harmonic frequency, alpha = w_e sqrt(mu / (2 D_e))
-with mu the pair's reduced mass.  The ``re`` and ``max`` guesses and the DVR
-grid are kept but not needed: the levels are Bohr-Sommerfeld, and the
-library finds the pair shapes itself.  A null seed is replaced by one drawn
-from the operating system and reported.
+with mu the pair's reduced mass.  The ``re`` and ``max`` guesses are kept
+but not needed: the library finds the pair shapes itself.  The DVR grid of
+pair AB serves when a run asks for DVR levels (``levels="dvr"``).  A null
+seed is replaced by one drawn from the operating system and reported.
 
 Outputs (Sec. 3.3): the short form has one row per (E_c, b) with the summed
 product counts; the long form one row per trajectory with its product
@@ -70,7 +70,7 @@ class Calc:
     b: float
     seed: int
     seed_from_file: bool
-    dvr: dict                 # per pair: npts, xmin, xmax (kept, unused)
+    dvr: dict                 # per pair: npts, xmin, xmax (AB's used for DVR levels)
     guesses: dict             # per pair: re / max guesses (kept, unused)
 
 
@@ -125,16 +125,24 @@ def load_input(src) -> Calc:
 
 
 def run(calc: Calc, n_traj: int, b_values: Optional[Sequence[float]] = None,
-        device: int = 0, rk: Optional[int] = None, opts: Optional["Q.RunOpts"] = None):
+        device: int = 0, rk: Optional[int] = None, opts: Optional["Q.RunOpts"] = None,
+        levels: str = "bs"):
     """Run n_traj trajectories at each impact parameter (default: the file's
-    b) in one fused launch.  Returns a dict of host arrays: the instance rows
-    (E_c, b), per-instance result rows, and per-trajectory outputs."""
+    b) in one fused launch.  levels: "bs" (Bohr-Sommerfeld) or "dvr" (the
+    file's DVR grid of pair AB).  Returns a dict of host arrays: the
+    instance rows (E_c, b), per-instance result rows, and per-trajectory
+    outputs."""
     import qcams_workloads as W
     bs = [calc.b] if b_values is None else [float(b) for b in b_values]
     params = calc.params if rk is None else dataclasses.replace(calc.params, rk=rk)
     inst = [W.Instance(calc.Ec_K, calc.v, calc.j, n_traj, k * n_traj, calc.seed, W.B_FIXED, b, 0.0)
             for k, b in enumerate(bs)]
     ctx = Q.Context(calc.system, params, device=device, masses_me=calc.system.masses_me)
+    if levels == "dvr":
+        g = calc.dvr["AB"]
+        ctx.set_level_method(Q.LEVELS_DVR, int(g["npts"]), float(g["xmin"]), float(g["xmax"]))
+    elif levels != "bs":
+        raise ValueError("levels must be 'bs' or 'dvr'")
     ctx.set_instances(inst)
     buf = ctx.new_run_buffers()
     ctx.run(buf, opts)
@@ -222,10 +230,12 @@ def main(argv=None):
     ap.add_argument("--short", default=None, help="short CSV (appended)")
     ap.add_argument("--long", default=None, help="long CSV (appended)")
     ap.add_argument("--rk", type=int, default=None, help="0: DOPRI5 (default), 1: DOP853")
+    ap.add_argument("--levels", default="bs", choices=["bs", "dvr"],
+                    help="internal energies: Bohr-Sommerfeld or the file's DVR grid")
     ap.add_argument("--device", type=int, default=0)
     a = ap.parse_args(argv)
     calc = load_input(a.input)
-    res = run(calc, a.n, _b_values(a.b), device=a.device, rk=a.rk)
+    res = run(calc, a.n, _b_values(a.b), device=a.device, rk=a.rk, levels=a.levels)
     if a.short:
         write_short(a.short, res)
     if a.long:
