@@ -132,9 +132,12 @@ QD void sqrt_rsqrt(double s, double& r, double& ir)
 }
 
 // e^x for x < 709: Cody-Waite reduction x = n ln2 + r, |r| <= ln2/2, with
-// ln2 split in a high part exact for |n| < 2^20 and a low correction, then
-// the Taylor series of e^r to degree 13 (truncation < 5e-18 relative) in
-// Horner form, scaled by 2^n.
+// ln2 split in a high part exact for |n| < 2^20 and a low correction, then a
+// degree-11 polynomial in Horner form, scaled by 2^n.  The polynomial
+// interpolates e^r at the 12 Chebyshev nodes of [-ln2/2, ln2/2] (solved in
+// 60-digit arithmetic, csrc/exp_poly.py); with its coefficients rounded to
+// double its relative error is below 1.7e-17, under the rounding of the
+// evaluation itself.
 QD double exp_cw(double x)
 {
     const double kLog2e = 1.4426950408889634074;
@@ -143,18 +146,16 @@ QD double exp_cw(double x)
     const double n = rint(x * kLog2e);
     double r = fma(-n, kLn2Hi, x);
     r = fma(-n, kLn2Lo, r);
-    double p = 1.0 / 6227020800.0;           // 1/13!
-    p = fma(p, r, 1.0 / 479001600.0);        // 1/12!
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
+    double p = 2.5110037605963777e-08;
+    p = fma(p, r, 2.763263963904103e-07);
+    p = fma(p, r, 2.755724091857897e-06);
+    p = fma(p, r, 2.4801485482328494e-05);
+    p = fma(p, r, 0.00019841269890047113);
+    p = fma(p, r, 0.0013888888952314775);
+    p = fma(p, r, 0.008333333333319601);
+    p = fma(p, r, 0.0416666666664881);
+    p = fma(p, r, 0.1666666666666668);
+    p = fma(p, r, 0.5000000000000019);
     p = fma(p, r, 1.0);
     p = fma(p, r, 1.0);
     return ldexp(p, (int)n);

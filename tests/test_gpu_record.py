@@ -52,13 +52,14 @@ def test_record_is_the_propagated_trajectory(Q, torch, rk):
     wl, ctx, st = _setup(Q, torch, prm, ids)
     st2 = Q.State(st.d.clone(), st.nstep.clone(), st.nrej.clone(), st.status.clone())
     ctx.propagate(st)
-    rec, cnt = ctx.propagate_record(st2, 200_000)
+    rmax = 100_000
+    rec, cnt = ctx.propagate_record(st2, rmax)
     torch.cuda.synchronize()
     for a, b in ((st.d, st2.d), (st.nstep, st2.nstep), (st.nrej, st2.nrej), (st.status, st2.status)):
         assert torch.equal(a, b)
     cnt = cnt.cpu().numpy()
     ns = st.nstep.cpu().numpy()
-    assert np.array_equal(cnt, ns + 1)
+    assert np.array_equal(cnt, np.minimum(ns + 1, rmax))
     d = st.d.cpu().numpy()
     r = rec.cpu().numpy()
     s = Q.make_system(wl.system)
@@ -67,8 +68,9 @@ def test_record_is_the_propagated_trajectory(Q, torch, rk):
     for c in range(len(ids)):
         pts = r[c, :cnt[c]]
         assert pts[0, 0] == 0.0 and np.all(np.diff(pts[:, 0]) > 0)
-        assert pts[-1, 0] == d[Q.F_T, c]
-        assert np.allclose(pts[-1, 1:], _pair_distances(d[:6, c], cA, cB), rtol=1e-14, atol=0)
+        if cnt[c] == ns[c] + 1:      # not truncated: the last point is the final state
+            assert pts[-1, 0] == d[Q.F_T, c]
+            assert np.allclose(pts[-1, 1:], _pair_distances(d[:6, c], cA, cB), rtol=1e-14, atol=0)
 
 
 def test_record_against_oracle_fixed_steps(Q, torch, orc):
