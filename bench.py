@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--learned", action="store_true",
                     help="also train the proposal network and report variance x GPU-seconds, "
                          "learned vs plain, for dissociation of H2(v=4,j=0)+Ca at 5e4 K")
-    ap.add_argument("--learned-replicates", type=int, default=16)
+    ap.add_argument("--learned-replicates", type=int, default=48)
     ap.add_argument("--learned-n", type=int, default=200_000)
     ap.add_argument("--learned-epochs", type=int, default=20)
     return ap.parse_args()
@@ -263,6 +263,7 @@ def learned_metric(args):
     c = L.compare(tw.system, tw.params, tgt, None if tr.fallback else tr.net, channel=Q.DISS,
                   n=args.learned_n, replicates=args.learned_replicates)
     return {"metric": "var(sigma_diss) x GPU-s, plain / learned", "value": c.efficiency,
+            "ci95": list(c.efficiency_ci95),
             "target": "H2(v=4,j=0)+Ca, 5e4 K, b by area to 10 a0, dissociation",
             "n_per_replicate": args.learned_n, "replicates": args.learned_replicates,
             "sigma_plain": float(c.sigma_plain[Q.DISS]), "sigma_learned": float(c.sigma_is[Q.DISS]),

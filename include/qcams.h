@@ -287,8 +287,9 @@ typedef struct {
     int32_t lanes;       /* lanes per trajectory: 1, or 4 (a quad shares the arithmetic of one
                             trajectory; 16 slots per wave).  Both give bit-identical
                             trajectories; 4 halves the latency of a step, 1 doubles the
-                            throughput.  0: 4 if the run has at most 4 trajectories per lane
-                            of a one-lane grid (bound by its longest trajectories), else 1 */
+                            throughput.  0: 4 when the expected step count of the longest
+                            trajectory exceeds 2.1 x the total over the lanes of a one-lane
+                            grid (a run bound by its longest trajectories), else 1 */
     int32_t pad;
 } qcams_run_opts;
 

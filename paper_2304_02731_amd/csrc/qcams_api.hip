@@ -47,6 +47,7 @@ struct qcams_ctx {
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
     qcams_run_opts last_opts{};                   // effective options of the last run
     bool lj126 = false;                           // pair AB is LJ 12-6
+    double cost_max = 0.0, cost_total = 0.0;      // expected steps: largest, summed
     int level_method = QCAMS_LEVELS_BS;           // levels of qcams_set_instances
     int dvr_npts = 0;
     double dvr_xmin = 0.0, dvr_xmax = 0.0;
@@ -1230,6 +1231,12 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
     }
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return cost[a] > cost[b]; });
+    c->cost_max = 0.0;
+    c->cost_total = 0.0;
+    for (int k = 0; k < n_inst; ++k) {
+        if (h[k].n_traj > 0) c->cost_max = std::max(c->cost_max, cost[k]);
+        c->cost_total += cost[k] * (double)h[k].n_traj;
+    }
     for (int r = 0; r < n_inst; ++r) loff[r + 1] = loff[r] + h[order[r]].n_traj;
     std::vector<int32_t> ident(n_inst);
     for (int k = 0; k < n_inst; ++k) ident[k] = k;
@@ -1330,15 +1337,17 @@ static int run_variant(const qcams_ctx* c, const qcams_run_opts* o)
     return o->rk == 1 ? 0 : (o->rk == 2 ? 1 : c->prm.rk);
 }
 
-// Lanes per trajectory of the persistent kernel.  Default: a quad when the
-// run has at most four trajectories per lane of a one-lane grid (the run is
-// then bound by its longest trajectories, whose steps the quad shortens),
-// else one lane (the run is bound by throughput, which one lane maximises).
+// Lanes per trajectory of the persistent kernel.  Default from the expected
+// step counts (~ 1/(v_c tau) per trajectory of an instance): the run is bound
+// by its longest trajectory (C, allowing 1.5x for the spread inside an
+// instance) or by its total work W over the L lanes of a one-lane grid.  A
+// quad takes about half the time per step but gives half the throughput,
+// so it is chosen when C > 2.1 W / L.
 static int run_width(const qcams_ctx* c, const qcams_run_opts* o)
 {
     if (o->lanes == 1 || o->lanes == 4) return o->lanes;
-    const int64_t blocks = o->blocks > 0 ? o->blocks : c->n_cu;
-    return c->n_total <= 4 * blocks * 256 ? 4 : 1;
+    const double L = 256.0 * (o->blocks > 0 ? o->blocks : c->n_cu);
+    return 1.5 * c->cost_max > 2.1 * c->cost_total / L ? 4 : 1;
 }
 
 // The run is three launch groups: the small set-up kernels (work order,

@@ -97,6 +97,7 @@ class Comparison:
     gpu_s_is: float
     proposal_s: float
     efficiency: float
+    efficiency_ci95: tuple    # from the F distribution of the variance ratio
     ess: float
     fallback: bool
     channel: int
@@ -155,5 +156,11 @@ def compare(system, params, target, net: Optional["Q.MLP"], channel: int = Q.DIS
     vi = float(np.var(si[:, channel], ddof=1))
     Tp, Ti = float(tp.mean()), float(ti.mean()) + (0.0 if fallback else prop_s / replicates)
     eff = (vp * Tp) / (vi * Ti) if vi > 0 else float("inf")
-    return Comparison(sp.mean(axis=0), si.mean(axis=0), vp, vi, Tp, Ti, prop_s, eff, ess, fallback,
-                      channel)
+    # the ratio of two sample variances of normal replicates, each with
+    # replicates - 1 degrees of freedom, scaled by the true ratio is F-distributed
+    from scipy import stats
+    dof = replicates - 1
+    lo, hi = stats.f.ppf([0.025, 0.975], dof, dof)
+    ci = (eff / hi, eff / lo) if vi > 0 else (float("inf"), float("inf"))
+    return Comparison(sp.mean(axis=0), si.mean(axis=0), vp, vi, Tp, Ti, prop_s, eff, ci, ess,
+                      fallback, channel)
