@@ -267,10 +267,13 @@ QD double dV_over_r(const Pot& P, double r, double ir)
 //   entries, (rho1 x, y, z, rho2 x, y, z).
 // W = 4: four consecutive lanes (a quad) share one trajectory.  Lane c < 3
 //   holds spatial component c -- entries (rho1_c, rho2_c) -- and evaluates
-//   pair c (AB, BC, CA) of the potential; lane 3 holds zeros and evaluates a
-//   copy of pair 0 that nobody reads.  Sums over the three spatial
-//   components (squared pair distances, error norms) are taken in one tree,
-//   (s_0 + s_1) + s_2, in both layouts (the quad adds s_3 = +0 to s_2, which
+//   pair c (AB, BC, CA) of the potential; lane 3 holds zeros and its pair
+//   value is never read.  The squared distance of pair p is summed as
+//   (q_p + q_p+1) + q_p+2 over its components (indices mod 3) in both
+//   layouts: in the quad, lane c also forms component c of pairs c - 1 and
+//   c + 1, and lane p collects the other two squares of its own pair from
+//   lanes p + 1 and p + 2 with two rotations.  Error norms are summed as
+//   (s_0 + s_1) + s_2 in both layouts (the quad adds s_3 = +0 to s_2, which
 //   is exact for the non-negative terms summed here); every other operation
 //   acts on one component with the same expression.  The layouts therefore
 //   give bit-identical trajectories (with contraction limited to single
@@ -282,16 +285,27 @@ template <int W> struct Lay;
 template <> struct Lay<1> { static constexpr int NC = 3; };
 template <> struct Lay<4> { static constexpr int NC = 1; };
 
-// A lane's part in its quad (W = 4 only).
+// A lane's part in its quad (W = 4 only).  Component c of pair q is
+// fma(a_q, rho1_c, b_q rho2_c) with (a, b) = (1, 0), (-cA, 1), (-cB, -1) for
+// AB, BC, CA (b rho2 is exact, so this rounds as the one-lane expressions).
 struct Role {
-    int c;     // spatial component and pair, 0..3
-    Pot pot;   // pair c's potential (pair 0 for c = 3)
+    int c;          // spatial component and pair, 0..3
+    Pot pot;        // pair c's potential (pair 0 for c = 3)
+    double a[3];    // (a, b) of pairs c, c - 1, c + 1 (zeros on lane 3)
+    double b[3];
+    double rin2;    // pair c's squared collapse radius
 };
 
 QD Role make_role(const Sys& S, int c)
 {
     Role R;
     R.c = c;
+    for (int k = 0; k < 3; ++k) {
+        const int q = c < 3 ? (k == 0 ? c : (k == 1 ? (c + 2) % 3 : (c + 1) % 3)) : -1;
+        R.a[k] = q == 0 ? 1.0 : (q == 1 ? -S.cA : (q == 2 ? -S.cB : 0.0));
+        R.b[k] = q == 1 ? 1.0 : (q == 2 ? -1.0 : 0.0);
+    }
+    R.rin2 = c == 1 ? S.rin2[1] : (c == 2 ? S.rin2[2] : S.rin2[0]);
     const Pot& a = S.pot[0];
     const Pot& b = S.pot[1];
     const Pot& e = S.pot[2];
@@ -310,6 +324,8 @@ QD Role make_role(const Sys& S, int c)
 // broadcasts lane k.
 constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E;
 template <int K> struct Bc { static constexpr int ctrl = K * 0x55; };
+// lane l < 3 reads lane (l + 1) mod 3, resp. (l + 2) mod 3; lane 3 itself
+constexpr int kDppNext = 0xC9, kDppPrev = 0xD2;
 
 // (bound_ctrl set: no lane reads outside its quad, so no "old" value is
 // needed and none is materialised)
@@ -328,6 +344,12 @@ __device__ inline int quad_and(int v)
     return v & __builtin_amdgcn_mov_dpp(v, kDppXor2, 0xF, 0xF, true);
 }
 
+__device__ inline int quad_or(int v)
+{
+    v |= __builtin_amdgcn_mov_dpp(v, kDppXor1, 0xF, 0xF, true);
+    return v | __builtin_amdgcn_mov_dpp(v, kDppXor2, 0xF, 0xF, true);
+}
+
 // (s_0 + s_1) + (s_2 + s_3) over the quad, the same value in all four lanes
 __device__ inline double quad_sum(double v)
 {
@@ -341,28 +363,32 @@ __device__ inline double quad_sum(double v)
 // force F(x) = -dV/dx is evaluated.  READING of the Jacobi signs (not fixed by
 // the paper): rho1 = r_B - r_A, rho2 = r_C - R_cm(AB); pair vectors
 // r_AB = rho1, r_BC = rho2 - cA rho1, r_CA = -rho2 - cB rho1.
-// Outputs the squared pair distances (for the stop rules) as a by-product;
-// in the quad layout every lane gets all three.
+// Outputs the squared pair distances (for the stop rules) as a by-product:
+// all three in the one-lane layout, the lane's own pair in the quad.
 // ---------------------------------------------------------------------------
 template <int W, int K0, int K1, int K2>
 QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double* s2)
 {
     constexpr int NC = Lay<W>::NC;
-    double rab[NC], rbc[NC], rca[NC], qab[NC], qbc[NC], qca[NC];
+    double rab[NC], rbc[NC], rca[NC];
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
         rab[a] = x[a];
         rbc[a] = fma(-S.cA, x[a], x[NC + a]);
         rca[a] = fma(-S.cB, x[a], -x[NC + a]);
-        qab[a] = rab[a] * rab[a];
-        qbc[a] = rbc[a] * rbc[a];
-        qca[a] = rca[a] * rca[a];
     }
-    double sab, sbc, sca, gab, gbc, gca;
+    double sab = 0.0, sbc = 0.0, sca = 0.0, gab, gbc, gca;
     if constexpr (W == 1) {
+        double qab[3], qbc[3], qca[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            qab[a] = rab[a] * rab[a];
+            qbc[a] = rbc[a] * rbc[a];
+            qca[a] = rca[a] * rca[a];
+        }
         sab = (qab[0] + qab[1]) + qab[2];
-        sbc = (qbc[0] + qbc[1]) + qbc[2];
-        sca = (qca[0] + qca[1]) + qca[2];
+        sbc = (qbc[1] + qbc[2]) + qbc[0];
+        sca = (qca[2] + qca[0]) + qca[1];
         double dab, dbc, dca, iab, ibc, ica;
         sqrt_rsqrt(sab, dab, iab);
         sqrt_rsqrt(sbc, dbc, ibc);
@@ -371,10 +397,17 @@ QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double*
         gbc = dV_over_r<K1>(S.pot[1], dbc, ibc);
         gca = dV_over_r<K2>(S.pot[2], dca, ica);
     } else {
-        sab = quad_sum(qab[0]);
-        sbc = quad_sum(qbc[0]);
-        sca = quad_sum(qca[0]);
-        const double s = R.c == 1 ? sbc : (R.c == 2 ? sca : sab);
+        // component c of pairs c, c - 1, c + 1; pair p's squares gathered on
+        // lane p in the order (q_p + q_p+1) + q_p+2
+        const double u0 = fma(R.a[0], x[0], R.b[0] * x[1]);
+        const double u1 = fma(R.a[1], x[0], R.b[1] * x[1]);
+        const double u2 = fma(R.a[2], x[0], R.b[2] * x[1]);
+        // (squares as separate statements: no contraction into the sums)
+        const double q0 = u0 * u0;
+        const double q1 = u1 * u1;
+        const double q2 = u2 * u2;
+        const double s = (q0 + quad_perm<kDppNext>(q1)) + quad_perm<kDppPrev>(q2);
+        sab = s;
         double d, id;
         sqrt_rsqrt(s, d, id);
         // one kind for all pairs: one specialised path; a specialised triple
@@ -558,21 +591,25 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
     const double g0 = hh * im0, g1 = hh * im1;
 #define IM(i) ((i) < NC ? im0 : im1)
 #define GG(i) ((i) < NC ? g0 : g1)
+    // h v = h p / mu, formed once per step for the stage positions
+    double hv[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) X[i] = fma(h * K[C2] * IM(i), p[i], x[i]);
+    for (int i = 0; i < N; ++i) hv[i] = (h * IM(i)) * p[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) X[i] = fma(K[C2], hv[i], x[i]);
     force_w<W, K0, K1, K2>(S, R, X, F2, junk);
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        X[i] = fma(GG(i), K[Q31] * F1[i], fma(h * K[C3] * IM(i), p[i], x[i]));
+        X[i] = fma(GG(i), K[Q31] * F1[i], fma(K[C3], hv[i], x[i]));
     force_w<W, K0, K1, K2>(S, R, X, F3, junk);
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        X[i] = fma(GG(i), fma(K[Q42], F2[i], K[Q41] * F1[i]), fma(h * K[C4] * IM(i), p[i], x[i]));
+        X[i] = fma(GG(i), fma(K[Q42], F2[i], K[Q41] * F1[i]), fma(K[C4], hv[i], x[i]));
     force_w<W, K0, K1, K2>(S, R, X, F4, junk);
 #pragma unroll
     for (int i = 0; i < N; ++i)
         X[i] = fma(GG(i), fma(K[Q53], F3[i], fma(K[Q52], F2[i], K[Q51] * F1[i])),
-                   fma(h * K[C5] * IM(i), p[i], x[i]));
+                   fma(K[C5], hv[i], x[i]));
     force_w<W, K0, K1, K2>(S, R, X, F5, junk);
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -737,6 +774,10 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
 #define GG(i) ((i) < NC ? g0 : g1)
 #pragma unroll
     for (int i = 0; i < N; ++i) F[0][i] = F1[i];
+    // h v = h p / mu, formed once per step for the stage positions
+    double hv[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) hv[i] = (h * IM(i)) * p[i];
 #pragma unroll
     for (int st = 1; st < NS; ++st) {
         double X[N];
@@ -746,7 +787,7 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
 #pragma unroll
             for (int l = 0; l < NS; ++l)
                 if (IX.q[st][l] >= 0) acc = fma(K[IX.q[st][l]], F[l][i], acc);
-            X[i] = fma(GG(i), acc, fma(h * K[IX.c[st]] * IM(i), p[i], x[i]));
+            X[i] = fma(GG(i), acc, fma(K[IX.c[st]], hv[i], x[i]));
         }
         force_w<W, K0, K1, K2>(S, R, X, F[st], junk);
     }
@@ -877,12 +918,21 @@ QD void lane_step_w(const Sys& S, const Role& R, const Prm& P, LaneW<W>& L)
         bool finite = true;
 #pragma unroll
         for (int i = 0; i < N; ++i) finite = finite && is_finite(xn[i]) && is_finite(pn[i]);
-        if constexpr (W == 4) finite = quad_and(finite ? 1 : 0) != 0;
-        const double m2 = fmax(s2[0], fmax(s2[1], s2[2]));
-        const bool collapsed = s2[0] < S.rin2[0] || s2[1] < S.rin2[1] || s2[2] < S.rin2[2];
+        bool collapsed, far;
+        if constexpr (W == 4) {
+            finite = quad_and(finite ? 1 : 0) != 0;
+            // each lane tests its own pair; lane 3 has none
+            const int own = R.c < 3 ? ((s2[0] < R.rin2 ? 1 : 0) | (s2[0] > L.rstop2 ? 2 : 0)) : 0;
+            const int any = quad_or(own);
+            collapsed = (any & 1) != 0;
+            far = (any & 2) != 0;
+        } else {
+            collapsed = s2[0] < S.rin2[0] || s2[1] < S.rin2[1] || s2[2] < S.rin2[2];
+            far = fmax(s2[0], fmax(s2[1], s2[2])) > L.rstop2;
+        }
         if (!finite) L.status = FAIL_NONFINITE;
         else if (collapsed) L.status = COLLAPSE;
-        else if (m2 > L.rstop2) L.status = OK_RSTOP;
+        else if (far) L.status = OK_RSTOP;
         else if (L.t >= L.tmax) L.status = OK_TMAX;
         if (!P.fixed_step) {
             double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * ctrl_pow<RK>(err)));
