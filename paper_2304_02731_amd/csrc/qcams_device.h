@@ -647,7 +647,10 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
         }
         part[c] = acc;
     }
-    return sqrt(comp_sum<W>(R, part) * (1.0 / 12.0));
+    const double m = comp_sum<W>(R, part) * (1.0 / 12.0);
+    double d, id;
+    sqrt_rsqrt(m, d, id);
+    return m > 0.0 ? d : m;   // 0, or NaN (rejected)
 }
 
 // ---------------------------------------------------------------------------
@@ -784,10 +787,15 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             double acc = 0.0;
+            bool any = false;
 #pragma unroll
             for (int l = 0; l < NS; ++l)
-                if (IX.q[st][l] >= 0) acc = fma(K[IX.q[st][l]], F[l][i], acc);
-            X[i] = fma(GG(i), acc, fma(K[IX.c[st]], hv[i], x[i]));
+                if (IX.q[st][l] >= 0) {
+                    acc = fma(K[IX.q[st][l]], F[l][i], acc);
+                    any = true;
+                }
+            X[i] = fma(K[IX.c[st]], hv[i], x[i]);
+            if (any) X[i] = fma(GG(i), acc, X[i]);
         }
         force_w<W, K0, K1, K2>(S, R, X, F[st], junk);
     }
@@ -834,7 +842,9 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
     }
     const double n5 = comp_sum<W>(R, part5), n3 = comp_sum<W>(R, part3);
     if (n5 == 0.0 && n3 == 0.0) return 0.0;
-    return n5 / sqrt((n5 + 0.01 * n3) * 12.0);
+    double d, id;
+    sqrt_rsqrt((n5 + 0.01 * n3) * 12.0, d, id);
+    return n5 * id;
 }
 
 // Starting step (Hairer-Norsett-Wanner I, Sec. II.4), on the 12-component
@@ -906,6 +916,7 @@ QD void lane_step_w(const Sys& S, const Role& R, const Prm& P, LaneW<W>& L)
         : dopri5_trial<W, K0, K1, K2>(S, R, L.x, L.p, L.F, hs, P.atol, P.rtol, xn, pn, Fn, s2);
     if (P.fixed_step) err = 0.0;
     if (!(err <= 1.0e300)) err = INFINITY;   // NaN or inf: reject
+    const double pw = 0.9 * ctrl_pow<RK>(err);
     if (err <= 1.0) {
         L.t = (hs == span) ? L.tmax : L.t + hs;
 #pragma unroll
@@ -915,9 +926,16 @@ QD void lane_step_w(const Sys& S, const Role& R, const Prm& P, LaneW<W>& L)
             L.F[i] = Fn[i];
         }
         L.nstep += 1;
-        bool finite = true;
+        // x - x is 0 for finite x, NaN otherwise
+        double z = 0.0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) finite = finite && is_finite(xn[i]) && is_finite(pn[i]);
+        for (int i = 0; i < N; ++i) {
+            const double zx = xn[i] - xn[i];
+            const double zp = pn[i] - pn[i];
+            z = z + zx;
+            z = z + zp;
+        }
+        bool finite = z == 0.0;
         bool collapsed, far;
         if constexpr (W == 4) {
             finite = quad_and(finite ? 1 : 0) != 0;
@@ -935,14 +953,14 @@ QD void lane_step_w(const Sys& S, const Role& R, const Prm& P, LaneW<W>& L)
         else if (far) L.status = OK_RSTOP;
         else if (L.t >= L.tmax) L.status = OK_TMAX;
         if (!P.fixed_step) {
-            double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * ctrl_pow<RK>(err)));
+            double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, pw));
             if (L.last_rej && fac > 1.0) fac = 1.0;
             L.h = hs * fac;
         }
         L.last_rej = 0;
     } else {
         L.nrej += 1;
-        L.h = hs * fmax(0.2, 0.9 * ctrl_pow<RK>(err));
+        L.h = hs * fmax(0.2, pw);
         L.last_rej = 1;
     }
     if (L.status == RUNNING && !P.fixed_step && L.h < 1e-12 * L.tmax) L.status = FAIL_HMIN;
