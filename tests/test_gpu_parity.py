@@ -333,6 +333,38 @@ def test_cross_sections_statistical(Q, torch, orc, rk):
     assert np.all(np.abs(dE[ok]) < 1e-8)
 
 
+def test_buckingham_collapse_matches_oracle(Q, torch, orc):
+    """A Buckingham B-C pair whose inner maximum (3.55 a0, 8.3e-3 Eh) is
+    crossed at 3e4 K (Sec. 3.2: the potential collapses inside it): the GPU
+    and the oracle stop the same trajectories as COLLAPSE, up to the few
+    whose outcome chaotic rounding decides; the COLLAPSE and quench fractions
+    agree within 3 combined standard errors."""
+    s = W.h2ca_system()
+    low = W.Pair("buck", {"A": 2.0, "b": 1.2, "C6": 40.0})
+    system = W.System(s.masses_amu, (s.pairs[0], low, s.pairs[2]), "h2 low-barrier buck")
+    inst = [W.Instance(3.0e4, 0, 0, 400, 0, 9090, W.B_AREA, 0.0, 6.0)]
+    wl = W.Workload("collapse", system, W.Params(rk=1), inst)
+    ctx = _ctx(Q, wl)
+    tid = ctx.all_ids()
+    n = tid.numel()
+    st = ctx.new_state(n)
+    ctx.init_conditions(tid, st)
+    ctx.propagate(st)
+    status_g = st.status.cpu().numpy().astype(np.int64)
+    recs, _ = orc.run_workload(wl, processes=8)
+    status_o = recs["status"].astype(np.int64)
+    assert np.all(status_g != Q.RUNNING)
+    for code in (Q.COLLAPSE, Q.OK_RSTOP):
+        pg, po = np.mean(status_g == code), np.mean(status_o == code)
+        comb = math.sqrt((pg * (1 - pg) + po * (1 - po)) / n)
+        assert abs(pg - po) <= 3 * comb + 1e-12, (code, pg, po, comb)
+    assert np.mean(status_g == Q.COLLAPSE) > 0.1
+    same = np.mean(status_g == status_o)
+    print("collapse GPU %.3f oracle %.3f, same status %.3f"
+          % (np.mean(status_g == Q.COLLAPSE), np.mean(status_o == Q.COLLAPSE), same))
+    assert same > 0.8
+
+
 # ----------------------------------------------------------------------------
 def test_empty_and_single(Q, torch):
     wl = W.config_small(n_traj=5)

@@ -126,12 +126,17 @@ def _system_cases():
     bc = W.Pair("buck", {"A": 50.0, "b": 1.5, "C6": 40.0})
     generic = W.System(s.masses_amu, (s.pairs[0], bc, s.pairs[2]), "h2 generic")
     mixed = W.config_mixed(per_inst=2)
+    # a Buckingham pair whose inner maximum (3.55 a0, 8.3e-3 Eh) is crossed
+    # at these energies: trajectories end in COLLAPSE, decided per pair lane
+    low = W.Pair("buck", {"A": 2.0, "b": 1.2, "C6": 40.0})
+    collapse = W.System(s.masses_amu, (s.pairs[0], low, s.pairs[2]), "h2 low-barrier buck")
     return {"all_morse": (s, _mixed_energy_workload(per=40).instances),
             "lj_morse_buck": (mixed.system, mixed.instances[::40]),
-            "generic": (generic, _mixed_energy_workload(per=40).instances)}
+            "generic": (generic, _mixed_energy_workload(per=40).instances),
+            "buck_collapse": (collapse, _mixed_energy_workload(per=40).instances)}
 
 
-@pytest.mark.parametrize("case", ["all_morse", "lj_morse_buck", "generic"])
+@pytest.mark.parametrize("case", ["all_morse", "lj_morse_buck", "generic", "buck_collapse"])
 @pytest.mark.parametrize("rk", [1, 2], ids=["dopri5", "dop853"])
 def test_quad_lanes_equal_single_lane(Q, torch, case, rk):
     """The quad layout (four lanes per trajectory, DPP exchanges) gives the
@@ -148,7 +153,10 @@ def test_quad_lanes_equal_single_lane(Q, torch, case, rk):
         snaps.append(_snapshot(buf))
     _same(snaps[0], snaps[1])
     assert np.all(snaps[0]["status"] != Q.RUNNING)
-    print(case, "labels", np.bincount(snaps[0]["label"], minlength=6))
+    if case == "buck_collapse":
+        assert np.any(snaps[0]["status"] == Q.COLLAPSE)
+    print(case, "labels", np.bincount(snaps[0]["label"], minlength=6),
+          "status", np.bincount(snaps[0]["status"], minlength=7))
 
 
 def test_graph_replays_match_eager(Q, torch):
