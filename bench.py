@@ -91,10 +91,11 @@ def cpu_baseline(wl, stride, procs):
     t0 = time.perf_counter()
     recs, _ = oracle.run_workload(wl, per, processes=procs)
     dt = time.perf_counter() - t0
+    nth = {1: "", 2: "2nd ", 3: "3rd "}.get(stride, "%dth " % stride)
     return {"value": n / dt, "unit": "trajectories/s", "cores": procs, "kind": "oracle",
-            "sample": "every %dth trajectory id of all %d instances (%d trajectories), "
+            "sample": "every %strajectory id of all %d instances (%d trajectories), "
                       "serial C oracle in a %d-process pool, %.1f s"
-                      % (stride, len(wl.instances), n, procs, dt)}
+                      % (nth, len(wl.instances), n, procs, dt)}
 
 
 def main():
