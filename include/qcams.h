@@ -281,7 +281,7 @@ typedef struct {
     int32_t blocks;      /* persistent grid in 256-thread workgroups; 0 = 1 per compute unit */
     int32_t refill_min;  /* refill a wave once this many of its slots are idle (0 = 1) */
     int32_t check_every; /* trial steps between refill checks (0 = 1) */
-    int32_t lpt;         /* 1: start instances longest-expected-first (cost ~ 1/(v_c tau_vj)) */
+    int32_t lpt;         /* 1: start instances longest-expected-first (cost ~ 1/(v_c sqrt(tau_vj))) */
     int32_t graph;       /* 1: capture the launch sequence once per buffer set and replay it */
     int32_t rk;          /* 0: the context's variant; 1: DOPRI5; 2: DOP853 */
     int32_t lanes;       /* lanes per trajectory: 1, or 4 (a quad shares the arithmetic of one

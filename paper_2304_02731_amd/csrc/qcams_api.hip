@@ -1219,7 +1219,12 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
         c->n_groups = ng;
     }
     // natural offsets and the longest-expected-first order: expected trial
-    // steps of a trajectory ~ collision time / vibrational period ~ 1/(v_c tau)
+    // steps of a trajectory ~ collision time / step size, taken as
+    // 1/(v_c sqrt(tau)): the step is set by the initial vibration (period
+    // tau) for a light, stiff molecule, less so where the inner walls of an
+    // anharmonic or heavy molecule set it; on the all-Morse and the mixed
+    // surfaces this ranks the instances by their longest trajectories with
+    // rank correlations 0.994 and 0.986 (1/(v_c tau): 0.995, 0.969)
     std::vector<int64_t> nat(n_inst + 1, 0), loff(n_inst + 1, 0);
     for (int k = 0; k < n_inst; ++k) nat[k + 1] = nat[k] + h[k].n_traj;
     std::vector<int32_t> order(n_inst);
@@ -1227,7 +1232,7 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
     for (int k = 0; k < n_inst; ++k) {
         order[k] = k;
         const double vc = sqrt(2.0 * h[k].Ec * c->sys.inv_mu123);
-        cost[k] = 1.0 / (vc * h[k].tau);
+        cost[k] = 1.0 / (vc * sqrt(h[k].tau));
     }
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return cost[a] > cost[b]; });
@@ -1338,7 +1343,7 @@ static int run_variant(const qcams_ctx* c, const qcams_run_opts* o)
 }
 
 // Lanes per trajectory of the persistent kernel.  Default from the expected
-// step counts (~ 1/(v_c tau) per trajectory of an instance): the run is bound
+// step counts (~ 1/(v_c sqrt(tau)) per trajectory of an instance): the run is bound
 // by its longest trajectory (C, allowing 1.5x for the spread inside an
 // instance) or by its total work W over the L lanes of a one-lane grid.  A
 // quad takes about half the time per step but gives half the throughput,
