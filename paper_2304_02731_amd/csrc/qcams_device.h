@@ -560,6 +560,13 @@ QD kcoef_t* dp_coefs()
 #endif
 }
 
+// acc + a b, or a b alone for the first term of a sum (a product, not an
+// FMA with a zero addend: the same value, counted as one operation)
+QD double mac(bool first, double a, double b, double acc)
+{
+    return first ? a * b : fma(a, b, acc);
+}
+
 // Sum over the spatial components c of per-component partial sums, in the
 // tree shared by both layouts (lane 3 of a quad contributes +0).
 template <int W>
@@ -643,7 +650,7 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
             const double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
             const double sp = fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol);
             const double qx = ex[i] * rcp_nr(sx), qp = epi * rcp_nr(sp);
-            acc = fma(qx, qx, fma(qp, qp, acc));
+            acc = fma(qx, qx, mac(k == 0, qp, qp, acc));
         }
         part[c] = acc;
     }
@@ -791,7 +798,7 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
 #pragma unroll
             for (int l = 0; l < NS; ++l)
                 if (IX.q[st][l] >= 0) {
-                    acc = fma(K[IX.q[st][l]], F[l][i], acc);
+                    acc = mac(!any, K[IX.q[st][l]], F[l][i], acc);
                     any = true;
                 }
             X[i] = fma(K[IX.c[st]], hv[i], x[i]);
@@ -803,14 +810,15 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         double sx = 0.0, sp = 0.0, a5 = 0.0, a3 = 0.0, b5 = 0.0, b3 = 0.0;
+        bool fx = true, fp = true, f5 = true, f3 = true, g5 = true, g3 = true;
 #pragma unroll
         for (int l = 0; l < NS; ++l) {
-            if (IX.bA[l] >= 0) sx = fma(K[IX.bA[l]], F[l][i], sx);
-            if (IX.b[l] >= 0) sp = fma(K[IX.b[l]], F[l][i], sp);
-            if (IX.e5A[l] >= 0) a5 = fma(K[IX.e5A[l]], F[l][i], a5);
-            if (IX.e3A[l] >= 0) a3 = fma(K[IX.e3A[l]], F[l][i], a3);
-            if (IX.e5[l] >= 0) b5 = fma(K[IX.e5[l]], F[l][i], b5);
-            if (IX.e3[l] >= 0) b3 = fma(K[IX.e3[l]], F[l][i], b3);
+            if (IX.bA[l] >= 0) { sx = mac(fx, K[IX.bA[l]], F[l][i], sx); fx = false; }
+            if (IX.b[l] >= 0) { sp = mac(fp, K[IX.b[l]], F[l][i], sp); fp = false; }
+            if (IX.e5A[l] >= 0) { a5 = mac(f5, K[IX.e5A[l]], F[l][i], a5); f5 = false; }
+            if (IX.e3A[l] >= 0) { a3 = mac(f3, K[IX.e3A[l]], F[l][i], a3); f3 = false; }
+            if (IX.e5[l] >= 0) { b5 = mac(g5, K[IX.e5[l]], F[l][i], b5); g5 = false; }
+            if (IX.e3[l] >= 0) { b3 = mac(g3, K[IX.e3[l]], F[l][i], b3); g3 = false; }
         }
         xn[i] = fma(GG(i), sx, fma(h * IM(i), p[i], x[i]));
         pn[i] = fma(h, sp, p[i]);
@@ -834,8 +842,8 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
             const double isx = rcp_nr(fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol));
             const double isp = rcp_nr(fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol));
             const double a = ex5[i] * isx, b = e5p * isp, cc = ex3[i] * isx, d = e3p * isp;
-            n5 = fma(a, a, fma(b, b, n5));
-            n3 = fma(cc, cc, fma(d, d, n3));
+            n5 = fma(a, a, mac(k == 0, b, b, n5));
+            n3 = fma(cc, cc, mac(k == 0, d, d, n3));
         }
         part5[c] = n5;
         part3[c] = n3;
