@@ -102,17 +102,16 @@ QD double ipow(double x, int n)
 }
 
 // ---------------------------------------------------------------------------
-// fast FP64 helpers for the inner loop (hardware estimates refined to full
-// double precision; a few ulp at most, which the parity bars absorb)
+// fast FP64 helpers for the inner loop (hardware estimates refined by
+// Newton or Goldschmidt steps)
 // ---------------------------------------------------------------------------
-// 1/x: v_rcp_f64 estimate and two Newton steps y <- y (2 - x y)
-QD double rcp_nr(double x)
+// 1/x to about 2e-15 relative: the v_rcp_f64 estimate (5e-8) and one Newton step
+// y <- y (2 - x y).  Used for the error-norm weights only, whose rounding
+// moves the accept threshold err <= 1 by that much.
+QD double rcp_norm(double x)
 {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
 }
 
 // sqrt(s) and 1/sqrt(s) for s > 0: v_rsq_f64 estimate and two coupled
@@ -240,7 +239,8 @@ QD double dV_over_r(const Pot& P, double r, double ir)
 {
     const int kind = K >= 0 ? (K == LJ126 ? LJ : K) : P.kind;
     if (kind == MORSE) {
-        const double e = exp_cw(P.p2 * (P.p1 - r));
+        // -alpha (r - re) as one FMA (alpha re is loop-invariant)
+        const double e = exp_cw(fma(-P.p2, r, P.p2 * P.p1));
         return (2.0 * P.p0 * P.p2) * (e - e * e) * ir;
     } else if (kind == LJ) {
         double tn, tm;
@@ -268,17 +268,17 @@ QD double dV_over_r(const Pot& P, double r, double ir)
 // W = 4: four consecutive lanes (a quad) share one trajectory.  Lane c < 3
 //   holds spatial component c -- entries (rho1_c, rho2_c) -- and evaluates
 //   pair c (AB, BC, CA) of the potential; lane 3 holds zeros and its pair
-//   value is never read.  The squared distance of pair p is summed as
-//   (q_p + q_p+1) + q_p+2 over its components (indices mod 3) in both
-//   layouts: in the quad, lane c also forms component c of pairs c - 1 and
-//   c + 1, and lane p collects the other two squares of its own pair from
-//   lanes p + 1 and p + 2 with two rotations.  Error norms are summed as
+//   value is never read.  The squared distance of pair p is formed as
+//   r_p+2^2 + (r_p+1^2 + r_p^2) over its components r (indices mod 3, FMAs)
+//   in both layouts: in the quad, lane c also forms component c of pairs
+//   c - 1 and c + 1, and lane p collects the other two components of its
+//   own pair from lanes p + 1 and p + 2 with two rotations.  Error norms are summed as
 //   (s_0 + s_1) + s_2 in both layouts (the quad adds s_3 = +0 to s_2, which
 //   is exact for the non-negative terms summed here); every other operation
 //   acts on one component with the same expression.  The layouts therefore
 //   give bit-identical trajectories (with contraction limited to single
 //   expressions, -ffp-contract=on).  W = 4 cuts the instructions a lane
-//   issues per step to about 40 %, for the long trajectories whose latency
+//   issues per step to about 45 %, for the long trajectories whose latency
 //   bounds a run.
 // ---------------------------------------------------------------------------
 template <int W> struct Lay;
@@ -379,16 +379,11 @@ QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double*
     }
     double sab = 0.0, sbc = 0.0, sca = 0.0, gab, gbc, gca;
     if constexpr (W == 1) {
-        double qab[3], qbc[3], qca[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            qab[a] = rab[a] * rab[a];
-            qbc[a] = rbc[a] * rbc[a];
-            qca[a] = rca[a] * rca[a];
-        }
-        sab = (qab[0] + qab[1]) + qab[2];
-        sbc = (qbc[1] + qbc[2]) + qbc[0];
-        sca = (qca[2] + qca[0]) + qca[1];
+        // pair p: r_p+2^2 + (r_p+1^2 + r_p^2) with component indices mod 3
+        // (the quad's order)
+        sab = fma(rab[2], rab[2], fma(rab[1], rab[1], rab[0] * rab[0]));
+        sbc = fma(rbc[0], rbc[0], fma(rbc[2], rbc[2], rbc[1] * rbc[1]));
+        sca = fma(rca[1], rca[1], fma(rca[0], rca[0], rca[2] * rca[2]));
         double dab, dbc, dca, iab, ibc, ica;
         sqrt_rsqrt(sab, dab, iab);
         sqrt_rsqrt(sbc, dbc, ibc);
@@ -397,16 +392,14 @@ QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double*
         gbc = dV_over_r<K1>(S.pot[1], dbc, ibc);
         gca = dV_over_r<K2>(S.pot[2], dca, ica);
     } else {
-        // component c of pairs c, c - 1, c + 1; pair p's squares gathered on
-        // lane p in the order (q_p + q_p+1) + q_p+2
+        // component c of pairs c, c - 1, c + 1; pair p's other two
+        // components gathered on lane p
         const double u0 = fma(R.a[0], x[0], R.b[0] * x[1]);
         const double u1 = fma(R.a[1], x[0], R.b[1] * x[1]);
         const double u2 = fma(R.a[2], x[0], R.b[2] * x[1]);
-        // (squares as separate statements: no contraction into the sums)
-        const double q0 = u0 * u0;
-        const double q1 = u1 * u1;
-        const double q2 = u2 * u2;
-        const double s = (q0 + quad_perm<kDppNext>(q1)) + quad_perm<kDppPrev>(q2);
+        const double v1 = quad_perm<kDppNext>(u1);   // component p + 1 of pair p
+        const double v2 = quad_perm<kDppPrev>(u2);   // component p + 2 of pair p
+        const double s = fma(v2, v2, fma(v1, v1, u0 * u0));
         sab = s;
         double d, id;
         sqrt_rsqrt(s, d, id);
@@ -646,10 +639,10 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int i = c + k * NC;
-            const double epi = h * fma(K[E7], F7[i], ep[i]);
+            const double epi = fma(K[E7], F7[i], ep[i]);
             const double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
             const double sp = fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol);
-            const double qx = ex[i] * rcp_nr(sx), qp = epi * rcp_nr(sp);
+            const double qx = ex[i] * rcp_norm(sx), qp = epi * (h * rcp_norm(sp));
             acc = fma(qx, qx, mac(k == 0, qp, qp, acc));
         }
         part[c] = acc;
@@ -837,10 +830,11 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int i = c + k * NC;
-            const double e5p = h * fma(K[IX.e5_13], F13[i], ep5[i]);
-            const double e3p = h * fma(K[IX.e3_13], F13[i], ep3[i]);
-            const double isx = rcp_nr(fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol));
-            const double isp = rcp_nr(fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol));
+            // (the h of the momentum errors folded into their weight)
+            const double e5p = fma(K[IX.e5_13], F13[i], ep5[i]);
+            const double e3p = fma(K[IX.e3_13], F13[i], ep3[i]);
+            const double isx = rcp_norm(fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol));
+            const double isp = h * rcp_norm(fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol));
             const double a = ex5[i] * isx, b = e5p * isp, cc = ex3[i] * isx, d = e3p * isp;
             n5 = fma(a, a, mac(k == 0, b, b, n5));
             n3 = fma(cc, cc, mac(k == 0, d, d, n3));

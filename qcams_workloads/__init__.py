@@ -198,7 +198,7 @@ def config_paper_grid(n_per_b: int = 10_000) -> Workload:
 # where its integrator keeps every trajectory of the workload inside the
 # |dE/E| < 1e-8 energy gate, and the timing-study values otherwise.  Measured
 # on the listed workloads (largest |dE/E| over all trajectories): DOP853 on
-# the batched workload 2.6e-9 at the example values; DOPRI5 on it 2.7e-8
+# the batched workload 4.8e-9 at the example values; DOPRI5 on it 2.7e-8
 # (fails), DOP853 on the sweep 1.1e-7 (fails), DOP853 on the mixed surface
 # 9.2e-9 (kept out: too close to the gate).
 TOL_EXAMPLE = (1.0e-10, 1.0e-11)
