@@ -30,12 +30,12 @@ if ROOT not in sys.path:
 # FP64 operations per trial step of one trajectory (FMA = 2), counted with
 # hardware FP64 instruction counters on a full-wave fixed-step run of the
 # one-lane propagation kernel, per surface and RK variant.
-F_STEP = {("morse", 0): 1851.7, ("morse", 1): 4032.7,
-          ("mixed", 0): 1725.6, ("mixed", 1): 3780.6}
+F_STEP = {("morse", 0): 1833.7, ("morse", 1): 3996.7,
+          ("mixed", 0): 1719.6, ("mixed", 1): 3768.6}
 # HBM bytes per launch of the persistent kernel from FETCH_SIZE and WRITE_SIZE
 # passes scaled by a streaming kernel of known size, for the kernel as it was
 # when the counters were taken (workload, kernel) -> bytes; null otherwise.
-TRAFFIC = {("batched", "k_persistent<4,0,0,0,1>"): 134.05e6}
+TRAFFIC = {("batched", "k_persistent<4,0,0,0,1>"): 134.74e6}
 RK_NAMES = {"dopri5": 0, "dop853": 1}
 KINDS = {"morse": "0,0,0", "mixed": "3,0,2"}   # 3: LJ 12-6 specialisation
 # workload -> (surface, default CPU-baseline stride)

@@ -114,9 +114,9 @@ QD double rcp_norm(double x)
     return fma(y, fma(-x, y, 1.0), y);
 }
 
-// sqrt(s) and 1/sqrt(s) for s > 0: v_rsq_f64 estimate and two coupled
+// sqrt(s) and 1/(2 sqrt(s)) for s > 0: v_rsq_f64 estimate and two coupled
 // Goldschmidt iterations (g -> sqrt(s), h -> 1/(2 sqrt(s))).
-QD void sqrt_rsqrt(double s, double& r, double& ir)
+QD void sqrt_hrsqrt(double s, double& r, double& hr)
 {
     const double y = __builtin_amdgcn_rsq(s);
     double g = s * y, h = 0.5 * y;
@@ -127,6 +127,14 @@ QD void sqrt_rsqrt(double s, double& r, double& ir)
     g = fma(g, e, g);
     h = fma(h, e, h);
     r = g;
+    hr = h;
+}
+
+// sqrt(s) and 1/sqrt(s) for s > 0
+QD void sqrt_rsqrt(double s, double& r, double& ir)
+{
+    double h;
+    sqrt_hrsqrt(s, r, h);
     ir = h + h;
 }
 
@@ -234,15 +242,19 @@ QD double pot_V(const Pot& P, double r)
 
 // V'(r)/r for the force, specialised per kind at compile time (K >= 0) or
 // selected at run time (K < 0; the kind is uniform across the wave).
+// hr = 1/(2r): the Morse force takes it with a doubled constant (the same
+// bits as 2 De alpha (e - e^2) / r), the other kinds double it.
 template <int K>
-QD double dV_over_r(const Pot& P, double r, double ir)
+QD double dV_over_r(const Pot& P, double r, double hr)
 {
     const int kind = K >= 0 ? (K == LJ126 ? LJ : K) : P.kind;
     if (kind == MORSE) {
         // -alpha (r - re) as one FMA (alpha re is loop-invariant)
         const double e = exp_cw(fma(-P.p2, r, P.p2 * P.p1));
-        return (2.0 * P.p0 * P.p2) * (e - e * e) * ir;
-    } else if (kind == LJ) {
+        return (4.0 * P.p0 * P.p2) * (e - e * e) * hr;
+    }
+    const double ir = hr + hr;
+    if (kind == LJ) {
         double tn, tm;
         if (K == LJ126) {
             // the 12-6 branch of lj_terms, without the run-time test
@@ -384,13 +396,13 @@ QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double*
         sab = fma(rab[2], rab[2], fma(rab[1], rab[1], rab[0] * rab[0]));
         sbc = fma(rbc[0], rbc[0], fma(rbc[2], rbc[2], rbc[1] * rbc[1]));
         sca = fma(rca[1], rca[1], fma(rca[0], rca[0], rca[2] * rca[2]));
-        double dab, dbc, dca, iab, ibc, ica;
-        sqrt_rsqrt(sab, dab, iab);
-        sqrt_rsqrt(sbc, dbc, ibc);
-        sqrt_rsqrt(sca, dca, ica);
-        gab = dV_over_r<K0>(S.pot[0], dab, iab);
-        gbc = dV_over_r<K1>(S.pot[1], dbc, ibc);
-        gca = dV_over_r<K2>(S.pot[2], dca, ica);
+        double dab, dbc, dca, hab, hbc, hca;   // distances, 1/(2 distance)
+        sqrt_hrsqrt(sab, dab, hab);
+        sqrt_hrsqrt(sbc, dbc, hbc);
+        sqrt_hrsqrt(sca, dca, hca);
+        gab = dV_over_r<K0>(S.pot[0], dab, hab);
+        gbc = dV_over_r<K1>(S.pot[1], dbc, hbc);
+        gca = dV_over_r<K2>(S.pot[2], dca, hca);
     } else {
         // component c of pairs c, c - 1, c + 1; pair p's other two
         // components gathered on lane p
@@ -401,20 +413,20 @@ QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double*
         const double v2 = quad_perm<kDppPrev>(u2);   // component p + 2 of pair p
         const double s = fma(v2, v2, fma(v1, v1, u0 * u0));
         sab = s;
-        double d, id;
-        sqrt_rsqrt(s, d, id);
+        double d, hd;
+        sqrt_hrsqrt(s, d, hd);
         // one kind for all pairs: one specialised path; a specialised triple
         // of kinds: each lane takes its pair's path (the wave runs all
         // three); otherwise the lane's own kind at run time
         double g;
         if constexpr (K0 >= 0 && K0 == K1 && K1 == K2) {
-            g = dV_over_r<K0>(R.pot, d, id);
+            g = dV_over_r<K0>(R.pot, d, hd);
         } else if constexpr (K0 >= 0 && K1 >= 0 && K2 >= 0) {
-            if (R.c == 1) g = dV_over_r<K1>(R.pot, d, id);
-            else if (R.c == 2) g = dV_over_r<K2>(R.pot, d, id);
-            else g = dV_over_r<K0>(R.pot, d, id);
+            if (R.c == 1) g = dV_over_r<K1>(R.pot, d, hd);
+            else if (R.c == 2) g = dV_over_r<K2>(R.pot, d, hd);
+            else g = dV_over_r<K0>(R.pot, d, hd);
         } else {
-            g = dV_over_r<-1>(R.pot, d, id);
+            g = dV_over_r<-1>(R.pot, d, hd);
         }
         gab = quad_perm<Bc<0>::ctrl>(g);
         gbc = quad_perm<Bc<1>::ctrl>(g);
@@ -919,52 +931,54 @@ QD void lane_step_w(const Sys& S, const Role& R, const Prm& P, LaneW<W>& L)
     if (P.fixed_step) err = 0.0;
     if (!(err <= 1.0e300)) err = INFINITY;   // NaN or inf: reject
     const double pw = 0.9 * ctrl_pow<RK>(err);
-    if (err <= 1.0) {
-        L.t = (hs == span) ? L.tmax : L.t + hs;
+    // Accept or reject by selects rather than branches: the tests below are
+    // evaluated on every trial and take effect only on acceptance.
+    const bool acc = err <= 1.0;
+    // x - x is 0 for finite x, NaN otherwise
+    double z = 0.0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            L.x[i] = xn[i];
-            L.p[i] = pn[i];
-            L.F[i] = Fn[i];
-        }
-        L.nstep += 1;
-        // x - x is 0 for finite x, NaN otherwise
-        double z = 0.0;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const double zx = xn[i] - xn[i];
-            const double zp = pn[i] - pn[i];
-            z = z + zx;
-            z = z + zp;
-        }
-        bool finite = z == 0.0;
-        bool collapsed, far;
-        if constexpr (W == 4) {
-            finite = quad_and(finite ? 1 : 0) != 0;
-            // each lane tests its own pair; lane 3 has none
-            const int own = R.c < 3 ? ((s2[0] < R.rin2 ? 1 : 0) | (s2[0] > L.rstop2 ? 2 : 0)) : 0;
-            const int any = quad_or(own);
-            collapsed = (any & 1) != 0;
-            far = (any & 2) != 0;
-        } else {
-            collapsed = s2[0] < S.rin2[0] || s2[1] < S.rin2[1] || s2[2] < S.rin2[2];
-            far = fmax(s2[0], fmax(s2[1], s2[2])) > L.rstop2;
-        }
-        if (!finite) L.status = FAIL_NONFINITE;
-        else if (collapsed) L.status = COLLAPSE;
-        else if (far) L.status = OK_RSTOP;
-        else if (L.t >= L.tmax) L.status = OK_TMAX;
-        if (!P.fixed_step) {
-            double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, pw));
-            if (L.last_rej && fac > 1.0) fac = 1.0;
-            L.h = hs * fac;
-        }
-        L.last_rej = 0;
-    } else {
-        L.nrej += 1;
-        L.h = hs * fmax(0.2, pw);
-        L.last_rej = 1;
+    for (int i = 0; i < N; ++i) {
+        const double zx = xn[i] - xn[i];
+        const double zp = pn[i] - pn[i];
+        z = z + zx;
+        z = z + zp;
     }
+    bool finite = z == 0.0;
+    bool collapsed, far;
+    if constexpr (W == 4) {
+        finite = quad_and(finite ? 1 : 0) != 0;
+        // each lane tests its own pair; lane 3 has none
+        const int own = R.c < 3 ? ((s2[0] < R.rin2 ? 1 : 0) | (s2[0] > L.rstop2 ? 2 : 0)) : 0;
+        const int any = quad_or(own);
+        collapsed = (any & 1) != 0;
+        far = (any & 2) != 0;
+    } else {
+        collapsed = s2[0] < S.rin2[0] || s2[1] < S.rin2[1] || s2[2] < S.rin2[2];
+        far = fmax(s2[0], fmax(s2[1], s2[2])) > L.rstop2;
+    }
+    const double tn = (hs == span) ? L.tmax : L.t + hs;
+    int st = L.status;
+    if (!finite) st = FAIL_NONFINITE;
+    else if (collapsed) st = COLLAPSE;
+    else if (far) st = OK_RSTOP;
+    else if (tn >= L.tmax) st = OK_TMAX;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        L.x[i] = acc ? xn[i] : L.x[i];
+        L.p[i] = acc ? pn[i] : L.p[i];
+        L.F[i] = acc ? Fn[i] : L.F[i];
+    }
+    L.t = acc ? tn : L.t;
+    L.status = acc ? st : L.status;
+    L.nstep += acc ? 1 : 0;
+    L.nrej += acc ? 0 : 1;
+    // new step: min(10, max(0.2, 0.9 err^-1/(q+1))) after an acceptance (10
+    // for err = 0; no increase right after a rejection), max(0.2, ...) after
+    // a rejection; a fixed step never changes (it is always accepted)
+    double fac = acc ? (err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, pw))) : fmax(0.2, pw);
+    if (acc && L.last_rej && fac > 1.0) fac = 1.0;
+    if (!P.fixed_step) L.h = hs * fac;
+    L.last_rej = acc ? 0 : 1;
     if (L.status == RUNNING && !P.fixed_step && L.h < 1e-12 * L.tmax) L.status = FAIL_HMIN;
     if (L.status == RUNNING && L.nstep >= P.max_steps) L.status = FAIL_MAXSTEPS;
 }
