@@ -98,15 +98,35 @@ __global__ void k_shapes(Pot p0, Pot p1, Pot p2, Shape* out, int* rc)
     out[i] = s;
 }
 
-__global__ void k_levels(Pot P, Shape Sh, double mu, int n, const int* v, const int* j,
-                         double* out, int* rc)
+// One wave per level: every lane runs the same root finding (the same
+// values, so the control flow is uniform) and lane k < kNQ evaluates
+// quadrature node k; the node sums are a butterfly over the wave, which
+// leaves the same bits in every lane.
+__global__ void __launch_bounds__(64) k_levels(Pot P, Shape Sh, double mu, int n, const int* v,
+                                               const int* j, double* out, int* rc)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x;
     if (i >= n) return;
+    const int k = threadIdx.x;
+    double st = 0.0, ct = 0.0;
+    if (k < kNQ) sincos(kPi * (k + 0.5) / kNQ, &st, &ct);
+    auto ap = [&](double J2, double E, double rm, double rp, double& act, double& per) {
+        const double c = 0.5 * (rp + rm), h = 0.5 * (rp - rm);
+        double a = 0.0, q = 0.0;
+        if (k < kNQ) ap_node(P, J2 / (2.0 * mu), E, c, h, st, ct, a, q);
+        for (int m = 32; m >= 1; m >>= 1) {
+            a += __shfl_xor(a, m);
+            q += __shfl_xor(q, m);
+        }
+        ap_finish(mu, h, a, q, act, per);
+    };
     double o[4] = {NAN, NAN, NAN, NAN};
-    rc[i] = bs_level(P, Sh, mu, v[i], j[i], o);
-    if (rc[i] != 0) o[0] = o[1] = o[2] = o[3] = NAN;
-    for (int k = 0; k < 4; ++k) out[4 * i + k] = o[k];
+    const int r = bs_level_with(P, Sh, mu, v[i], j[i], o, ap);
+    if (r != 0) o[0] = o[1] = o[2] = o[3] = NAN;
+    if (k == 0) {
+        rc[i] = r;
+        for (int f = 0; f < 4; ++f) out[4 * i + f] = o[f];
+    }
 }
 
 // turning points and period at given energies (the DVR levels)
@@ -1014,7 +1034,7 @@ int qcams_levels(qcams_ctx* c, int32_t n, const int32_t* v, const int32_t* j, do
     if (e == hipSuccess) e = hipMemcpy(dv, v, n * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dj, j, n * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_levels, dim3(grid_of(n, 64)), dim3(64), 0, 0, c->sys.pot[0],
+        hipLaunchKernelGGL(k_levels, dim3(n), dim3(64), 0, 0, c->sys.pot[0],
                            c->sys.shape[0], c->sys.mu12, n, dv, dj, dout, drc);
         e = hipGetLastError();
     }

@@ -106,8 +106,9 @@ QD double ipow(double x, int n)
 // Newton or Goldschmidt steps)
 // ---------------------------------------------------------------------------
 // 1/x to about 2e-15 relative: the v_rcp_f64 estimate (5e-8) and one Newton step
-// y <- y (2 - x y).  Used for the error-norm weights only, whose rounding
-// moves the accept threshold err <= 1 by that much.
+// y <- y (2 - x y).  Used where that suffices: the error-norm weights (it
+// moves the accept threshold err <= 1 by that much) and the centrifugal term
+// of the radial quadrature.
 QD double rcp_norm(double x)
 {
     const double y = __builtin_amdgcn_rcp(x);
@@ -181,7 +182,7 @@ QD double ctrl_pow(double err)
 QD void pot_morse(const Pot& P, double r, double& V, double& d1, double& d2)
 {
     const double De = P.p0, re = P.p1, a = P.p2;
-    const double e = exp(-a * (r - re));
+    const double e = exp_cw(-a * (r - re));
     const double om = 1.0 - e;
     V = De * om * om - De;
     d1 = 2.0 * De * a * e * om;
@@ -220,7 +221,7 @@ QD void pot_buck(const Pot& P, double r, double& V, double& d1, double& d2)
 {
     const double A = P.p0, b = P.p1, C6 = P.p2;
     const double ir = 1.0 / r, ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
-    const double ex = A * exp(-b * r);
+    const double ex = A * exp_cw(-b * r);
     V = ex - C6 * ir6;
     d1 = -b * ex + 6.0 * C6 * ir6 * ir;
     d2 = b * b * ex - 42.0 * C6 * ir6 * ir2;
@@ -1246,30 +1247,63 @@ QD bool turning_points(const Pot& P, const Shape& Sh, const Radial& R, double mu
 // the integrands of Eq. (10) and Eq. (7) become smooth, even and periodic in
 // theta, so the midpoint rule converges geometrically.
 //   act = (sqrt(2mu)/pi) int sqrt(E - V_eff) dr ; per = sqrt(2mu) int dr / sqrt(E - V_eff)
-QD void action_period(const Pot& P, double mu, double J2, double E, double rm, double rp,
-                      double& act, double& per)
+// ap_node gives one node's terms of the two sums (sin(theta) sqrt(E - V_eff)
+// and sin(theta) / sqrt(E - V_eff)); ap_finish scales the sums.
+QD void ap_node(const Pot& P, double cent, double E, double c, double h, double st, double ct,
+                double& a, double& q)
 {
-    const double c = 0.5 * (rp + rm), h = 0.5 * (rp - rm);
-    double sa = 0.0, sp = 0.0;
-    for (int k = 0; k < kNQ; ++k) {
-        double st, ct;
-        sincos(kPi * (k + 0.5) / kNQ, &st, &ct);
-        const double r = c + h * ct;
-        double kin = E - veff(P, mu, J2, r);
-        kin = fmax(kin, 0.0);
-        const double sq = sqrt(kin);
-        sa += st * sq;
-        sp += kin > 0.0 ? st / sq : 0.0;
+    const double r = c + h * ct;
+    const double ir = rcp_norm(r);
+    const double kin = E - (pot_V(P, r) + cent * (ir * ir));
+    a = 0.0;
+    q = 0.0;
+    if (kin > 0.0) {
+        double sq, isq;
+        sqrt_rsqrt(kin, sq, isq);
+        a = st * sq;
+        q = st * isq;
     }
+}
+
+QD void ap_finish(double mu, double h, double sa, double sp, double& act, double& per)
+{
     const double s2mu = sqrt(2.0 * mu);
     act = s2mu / kPi * h * (kPi / kNQ) * sa;
     per = s2mu * h * (kPi / kNQ) * sp;
 }
 
+QD void action_period(const Pot& P, double mu, double J2, double E, double rm, double rp,
+                      double& act, double& per)
+{
+    const double c = 0.5 * (rp + rm), h = 0.5 * (rp - rm);
+    const double cent = J2 / (2.0 * mu);
+    double sa = 0.0, sp = 0.0;
+    // nodes theta_k = pi (k + 1/2) / kNQ by rotation from theta_0 (the
+    // recurrence's rounding, a few ulp over kNQ steps, is far below the
+    // error of the rule)
+    double st, ct, sd, cd;
+    sincos(kPi * 0.5 / kNQ, &st, &ct);
+    sincos(kPi / kNQ, &sd, &cd);
+    for (int k = 0; k < kNQ; ++k) {
+        double a, q;
+        ap_node(P, cent, E, c, h, st, ct, a, q);
+        sa += a;
+        sp += q;
+        const double cn = fma(ct, cd, -st * sd);
+        st = fma(st, cd, ct * sd);
+        ct = cn;
+    }
+    ap_finish(mu, h, sa, sp, act, per);
+}
+
 // Bohr-Sommerfeld level of the AB molecule: E with act(E) = v + 1/2,
 // safeguarded Newton using d act/dE = per/(2 pi).  Returns 0, or -2 when the
-// level is not bound, -3 when a root cannot be bracketed.
-QD int bs_level(const Pot& P, const Shape& Sh, double mu, int v, int j, double* out)
+// level is not bound, -3 when a root cannot be bracketed.  `ap(J2, E, rm, rp,
+// act, per)` evaluates the action and period (serially, or one node per lane
+// of a wave).
+template <class AP>
+QD int bs_level_with(const Pot& P, const Shape& Sh, double mu, int v, int j, double* out,
+                     const AP& ap)
 {
     const double J2 = (double)j * (j + 1.0);
     const Radial R = radial(P, Sh, mu, J2);
@@ -1280,13 +1314,13 @@ QD int bs_level(const Pot& P, const Shape& Sh, double mu, int v, int j, double* 
     double lo = Elo, hi = Ehi - 1e-13 * fabs(Ehi - Elo);
     double rm, rp, act, per;
     if (!turning_points(P, Sh, R, mu, J2, hi, rm, rp)) return -2;
-    action_period(P, mu, J2, hi, rm, rp, act, per);
+    ap(J2, hi, rm, rp, act, per);
     if (!(act > target)) return -2;
     // start from the harmonic estimate near the bottom of the well
     double E = lo + (hi - lo) * fmin(0.5, target / act);
     for (int it = 0; it < 200; ++it) {
         if (!turning_points(P, Sh, R, mu, J2, E, rm, rp)) return -3;
-        action_period(P, mu, J2, E, rm, rp, act, per);
+        ap(J2, E, rm, rp, act, per);
         const double f = act - target;
         if (f < 0.0) lo = E; else hi = E;
         double En = E - f * 2.0 * kPi / per;
@@ -1296,12 +1330,20 @@ QD int bs_level(const Pot& P, const Shape& Sh, double mu, int v, int j, double* 
         if (done) break;
     }
     if (!turning_points(P, Sh, R, mu, J2, E, rm, rp)) return -3;
-    action_period(P, mu, J2, E, rm, rp, act, per);
+    ap(J2, E, rm, rp, act, per);
     out[0] = E;
     out[1] = rm;
     out[2] = rp;
     out[3] = per;
     return 0;
+}
+
+QD int bs_level(const Pot& P, const Shape& Sh, double mu, int v, int j, double* out)
+{
+    return bs_level_with(P, Sh, mu, v, j, out,
+                         [&](double J2, double E, double rm, double rp, double& act, double& per) {
+                             action_period(P, mu, J2, E, rm, rp, act, per);
+                         });
 }
 
 // Turning points and period of the AB pair at a given energy E of level
