@@ -738,6 +738,13 @@ constexpr Index index()
     return x;
 }
 constexpr Index IX = index();
+// first nonzero position of a coefficient row (the sum starts with a product)
+constexpr int first_nz(const int16_t (&row)[NS])
+{
+    for (int l = 0; l < NS; ++l)
+        if (row[l] >= 0) return l;
+    return NS;
+}
 static_assert(IX.n <= NV, "coefficient table too small");
 constexpr Vals vals()
 {
@@ -812,26 +819,32 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
         }
         force_w<W, K0, K1, K2>(S, R, X, F[st], junk);
     }
+    // the step's six coefficient sums, each in l order (coefficient order)
+    double sx[N], sp[N], a5[N], a3[N], b5[N], b3[N];
+#pragma unroll
+    for (int l = 0; l < NS; ++l) {
+        const bool fx = IX.bA[l] >= 0 && l == first_nz(IX.bA), fp = IX.b[l] >= 0 && l == first_nz(IX.b);
+        const bool f5 = IX.e5A[l] >= 0 && l == first_nz(IX.e5A), f3 = IX.e3A[l] >= 0 && l == first_nz(IX.e3A);
+        const bool g5 = IX.e5[l] >= 0 && l == first_nz(IX.e5), g3 = IX.e3[l] >= 0 && l == first_nz(IX.e3);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            if (IX.bA[l] >= 0) sx[i] = mac(fx, K[IX.bA[l]], F[l][i], sx[i]);
+            if (IX.b[l] >= 0) sp[i] = mac(fp, K[IX.b[l]], F[l][i], sp[i]);
+            if (IX.e5A[l] >= 0) a5[i] = mac(f5, K[IX.e5A[l]], F[l][i], a5[i]);
+            if (IX.e3A[l] >= 0) a3[i] = mac(f3, K[IX.e3A[l]], F[l][i], a3[i]);
+            if (IX.e5[l] >= 0) b5[i] = mac(g5, K[IX.e5[l]], F[l][i], b5[i]);
+            if (IX.e3[l] >= 0) b3[i] = mac(g3, K[IX.e3[l]], F[l][i], b3[i]);
+        }
+    }
     double ex5[N], ex3[N], ep5[N], ep3[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        double sx = 0.0, sp = 0.0, a5 = 0.0, a3 = 0.0, b5 = 0.0, b3 = 0.0;
-        bool fx = true, fp = true, f5 = true, f3 = true, g5 = true, g3 = true;
-#pragma unroll
-        for (int l = 0; l < NS; ++l) {
-            if (IX.bA[l] >= 0) { sx = mac(fx, K[IX.bA[l]], F[l][i], sx); fx = false; }
-            if (IX.b[l] >= 0) { sp = mac(fp, K[IX.b[l]], F[l][i], sp); fp = false; }
-            if (IX.e5A[l] >= 0) { a5 = mac(f5, K[IX.e5A[l]], F[l][i], a5); f5 = false; }
-            if (IX.e3A[l] >= 0) { a3 = mac(f3, K[IX.e3A[l]], F[l][i], a3); f3 = false; }
-            if (IX.e5[l] >= 0) { b5 = mac(g5, K[IX.e5[l]], F[l][i], b5); g5 = false; }
-            if (IX.e3[l] >= 0) { b3 = mac(g3, K[IX.e3[l]], F[l][i], b3); g3 = false; }
-        }
-        xn[i] = fma(GG(i), sx, fma(h * IM(i), p[i], x[i]));
-        pn[i] = fma(h, sp, p[i]);
-        ex5[i] = GG(i) * a5;
-        ex3[i] = GG(i) * a3;
-        ep5[i] = b5;
-        ep3[i] = b3;
+        xn[i] = fma(GG(i), sx[i], fma(h * IM(i), p[i], x[i]));
+        pn[i] = fma(h, sp[i], p[i]);
+        ex5[i] = GG(i) * a5[i];
+        ex3[i] = GG(i) * a3[i];
+        ep5[i] = b5[i];
+        ep3[i] = b3[i];
     }
 #undef IM
 #undef GG
