@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--refill-min", type=int, default=1)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-lpt", action="store_true")
-    ap.add_argument("--lanes", type=int, default=0, choices=[0, 1, 4],
+    ap.add_argument("--lanes", type=int, default=0, choices=[0, 1, 4, 8],
                     help="lanes per trajectory in the persistent kernel (0: by run size)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--learned", action="store_true",

@@ -284,18 +284,21 @@ typedef struct {
     int32_t lpt;         /* 1: start instances longest-expected-first (cost ~ 1/(v_c sqrt(tau_vj))) */
     int32_t graph;       /* 1: capture the launch sequence once per buffer set and replay it */
     int32_t rk;          /* 0: the context's variant; 1: DOPRI5; 2: DOP853 */
-    int32_t lanes;       /* lanes per trajectory: 1, or 4 (a quad shares the arithmetic of one
-                            trajectory; 16 slots per wave).  Both give bit-identical
-                            trajectories; 4 halves the latency of a step, 1 doubles the
-                            throughput.  0: 4 when the expected step count of the longest
-                            trajectory exceeds 2.1 x the total over the lanes of a one-lane
-                            grid (a run bound by its longest trajectories), else 1 */
+    int32_t lanes;       /* lanes per trajectory: 1, 4 (a quad shares the arithmetic of one
+                            trajectory; 16 slots per wave) or 8 (an octet; 8 slots per
+                            wave).  All give bit-identical trajectories; 4 halves the
+                            latency of a step, 8 takes about 5 % more off it, 1 has the
+                            highest throughput.  0: 8 when every trajectory fits in the
+                            grid's octet slots at once; else 4 when the expected step
+                            count of the longest trajectory exceeds 2.1 x the total over
+                            the lanes of a one-lane grid (a run bound by its longest
+                            trajectories); else 1 */
     int32_t pad;
 } qcams_run_opts;
 
 /* The whole hot path over every installed trajectory (N = sum of n_traj):
  * initial conditions, propagation in one persistent launch whose slots (a
- * lane or a quad of lanes) take a new trajectory as soon as theirs stops,
+ * lane, a quad or an octet of lanes) take a new trajectory as soon as theirs stops,
  * classification, and the
  * per-instance reduction of qcams_cross_sections.  Results are stored at
  * each trajectory's natural position p (instances in id order, ids
@@ -321,12 +324,12 @@ int qcams_last_run_kernel_ms(qcams_ctx *ctx, double *ms);
 
 /* The options the last qcams_run on this context took effect with: blocks,
  * refill_min and check_every as clamped, rk = 1 (DOPRI5) or 2 (DOP853),
- * lanes = 1 or 4.  host only.  Errors: EINVAL (no run yet). */
+ * lanes = 1, 4 or 8.  host only.  Errors: EINVAL (no run yet). */
 int qcams_last_run_options(qcams_ctx *ctx, qcams_run_opts *used);
 
 /* Choose fast qcams_run options on the installed instances -- install a
  * calibration subset first -- by timing runs: coordinate descent, two
- * sweeps from the defaults, over lanes per trajectory (4, 1), grid (1-4
+ * sweeps from the defaults, over lanes per trajectory (4, 1, 8), grid (1-4
  * workgroups per CU), refill_min (1, 4, 16), check_every (1, 4, 8) and
  * instance order (LPT, natural).  Returns the fastest in *best (graph off)
  * with its time in *best_ms (may be NULL).  Buffers as for qcams_run; each

@@ -380,13 +380,22 @@ __device__ inline void opaque_sgpr(T& v)
 // lane layouts of the device header); the idle-slot count and a slot's rank
 // among the idle slots are the lane counts divided by W.
 template <int W>
-__device__ inline void load_traj(const double* d, int64_t ld, int64_t pos, int c, LaneW<W>& L)
+__device__ inline void load_traj(const double* d, int64_t ld, int64_t pos, int c, int side,
+                                 LaneW<W>& L)
 {
     if constexpr (W == 1) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
             L.x[f] = d[f * ld + pos];
             L.p[f] = d[(6 + f) * ld + pos];
+        }
+    } else if constexpr (W == 8) {
+        // first quad: (rho1_c, P1_c); second quad: (rho2_c, P2_c)
+        if (c < 3) {
+            L.x[0] = d[(3 * side + c) * ld + pos];
+            L.p[0] = d[(6 + 3 * side + c) * ld + pos];
+        } else {
+            L.x[0] = L.p[0] = 0.0;
         }
     } else {
         if (c < 3) {
@@ -401,13 +410,19 @@ __device__ inline void load_traj(const double* d, int64_t ld, int64_t pos, int c
 }
 
 template <int W>
-__device__ inline void store_traj(double* d, int64_t ld, int64_t pos, int c, const LaneW<W>& L)
+__device__ inline void store_traj(double* d, int64_t ld, int64_t pos, int c, int side,
+                                  const LaneW<W>& L)
 {
     if constexpr (W == 1) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
             d[f * ld + pos] = L.x[f];
             d[(6 + f) * ld + pos] = L.p[f];
+        }
+    } else if constexpr (W == 8) {
+        if (c < 3) {
+            d[(3 * side + c) * ld + pos] = L.x[0];
+            d[(6 + 3 * side + c) * ld + pos] = L.p[0];
         }
     } else {
         if (c < 3) {
@@ -427,7 +442,8 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
     constexpr int SLOTS = 64 / W;
     const unsigned lane = __lane_id();
     const int c = W == 1 ? 0 : (int)(lane & 3u);
-    const Role R = make_role(S, c);
+    const int side = W == 8 ? (int)((lane >> 2) & 1u) : 0;
+    const Role R = make_role(S, c, side);
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     LaneW<W> L;
     int64_t pos = -1;
@@ -456,7 +472,7 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
                     opaque_sgpr(dr);
                     opaque_sgpr(l);
                     pos = M.order[w];
-                    load_traj<W>(dr, l, pos, c, L);
+                    load_traj<W>(dr, l, pos, c, side, L);
                     L.t = dr[QCAMS_F_T * l + pos];
                     L.tmax = dr[QCAMS_F_TMAX * l + pos];
                     const double rs = dr[QCAMS_F_RSTOP * l + pos];
@@ -488,8 +504,8 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
             int64_t l = ld;
             opaque_sgpr(dw);
             opaque_sgpr(l);
-            store_traj<W>(dw, l, pos, c, L);
-            if (c == 0) {
+            store_traj<W>(dw, l, pos, c, side, L);
+            if (c == 0 && side == 0) {
                 dw[QCAMS_F_T * l + pos] = L.t;
                 dw[QCAMS_F_H * l + pos] = L.h;
                 nstep[pos] = L.nstep;
@@ -855,7 +871,11 @@ struct PersistentL {
         RunMap M{order, c->n_total};
         Prm P = c->prm;
         P.rk = RK;
-        if (width == 4)
+        if (width == 8)
+            hipLaunchKernelGGL((k_persistent<8, K0, K1, K2, RK>), dim3(blocks), dim3(256), 0, s,
+                               c->sys, P, M, c->d_counter, refill_min, check_every, st->d,
+                               st->nstep, st->nrej, st->status, st->ld);
+        else if (width == 4)
             hipLaunchKernelGGL((k_persistent<4, K0, K1, K2, RK>), dim3(blocks), dim3(256), 0, s,
                                c->sys, P, M, c->d_counter, refill_min, check_every, st->d,
                                st->nstep, st->nrej, st->status, st->ld);
@@ -1362,16 +1382,20 @@ static int run_variant(const qcams_ctx* c, const qcams_run_opts* o)
     return o->rk == 1 ? 0 : (o->rk == 2 ? 1 : c->prm.rk);
 }
 
-// Lanes per trajectory of the persistent kernel.  Default from the expected
-// step counts (~ 1/(v_c sqrt(tau)) per trajectory of an instance): the run is bound
-// by its longest trajectory (C, allowing 1.5x for the spread inside an
-// instance) or by its total work W over the L lanes of a one-lane grid.  A
-// quad takes about half the time per step but gives half the throughput,
-// so it is chosen when C > 2.1 W / L.
+// Lanes per trajectory of the persistent kernel.  Default: an octet when
+// every trajectory fits in the grid's octet slots at once (the run is then
+// bound by its longest trajectory, and an octet step is about 5 % shorter
+// than a quad's); otherwise from the expected step counts (~ 1/(v_c
+// sqrt(tau)) per trajectory of an instance): the run is bound by its longest
+// trajectory (C, allowing 1.5x for the spread inside an instance) or by its
+// total work W over the L lanes of a one-lane grid.  A quad takes about
+// half the time per step but gives half the throughput, so it is chosen
+// when C > 2.1 W / L.
 static int run_width(const qcams_ctx* c, const qcams_run_opts* o)
 {
-    if (o->lanes == 1 || o->lanes == 4) return o->lanes;
+    if (o->lanes == 1 || o->lanes == 4 || o->lanes == 8) return o->lanes;
     const double L = 256.0 * (o->blocks > 0 ? o->blocks : c->n_cu);
+    if (8.0 * (double)c->n_total <= L) return 8;
     return 1.5 * c->cost_max > 2.1 * c->cost_total / L ? 4 : 1;
 }
 
@@ -1459,7 +1483,7 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
     o.graph = 0;
     if (opts) o = *opts;
     if (o.blocks < 0 || o.refill_min < 0 || o.check_every < 0 || o.rk < 0 || o.rk > 2 ||
-        (o.lanes != 0 && o.lanes != 1 && o.lanes != 4))
+        (o.lanes != 0 && o.lanes != 1 && o.lanes != 4 && o.lanes != 8))
         return fail(c, QCAMS_EINVAL, "invalid run option");
     for (const Inst& I : c->h_inst)
         if (I.b_mode == 2 && (!sample || !c->d_prop_q))
@@ -1681,10 +1705,10 @@ static int autotune_search(qcams_ctx* c, const qcams_state* st, const qcams_outc
     const int check_c[nc] = {1, 4, 8};
     for (int sweep = 0; sweep < 2 && rc == QCAMS_OK; ++sweep)
         for (int dim = 0; dim < 5 && rc == QCAMS_OK; ++dim) {
-            const int nv = dim == 0 ? 2 : dim == 1 ? nb : dim == 2 ? nr : dim == 3 ? nc : 2;
+            const int nv = dim == 0 ? 3 : dim == 1 ? nb : dim == 2 ? nr : dim == 3 ? nc : 2;
             for (int v = 0; v < nv && rc == QCAMS_OK; ++v) {
                 qcams_run_opts o = bo;
-                if (dim == 0) o.lanes = v == 0 ? 4 : 1;
+                if (dim == 0) o.lanes = v == 0 ? 4 : (v == 1 ? 1 : 8);
                 else if (dim == 1) o.blocks = blocks_c[v];
                 else if (dim == 2) o.refill_min = refill_c[v];
                 else if (dim == 3) o.check_every = check_c[v];

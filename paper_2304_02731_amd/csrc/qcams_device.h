@@ -295,24 +295,35 @@ QD double dV_over_r(const Pot& P, double r, double hr)
 //   bounds a run.
 // ---------------------------------------------------------------------------
 template <int W> struct Lay;
-template <> struct Lay<1> { static constexpr int NC = 3; };
-template <> struct Lay<4> { static constexpr int NC = 1; };
+// NC: spatial components per lane; N: state components (of x, and of p) per lane
+template <> struct Lay<1> { static constexpr int NC = 3, N = 6; };
+template <> struct Lay<4> { static constexpr int NC = 1, N = 2; };
+template <> struct Lay<8> { static constexpr int NC = 1, N = 1; };
 
 // A lane's part in its quad (W = 4 only).  Component c of pair q is
 // fma(a_q, rho1_c, b_q rho2_c) with (a, b) = (1, 0), (-cA, 1), (-cB, -1) for
 // AB, BC, CA (b rho2 is exact, so this rounds as the one-lane expressions).
 struct Role {
     int c;          // spatial component and pair, 0..3
+    int side;       // octet: 0 holds (rho1_c, P1_c), 1 holds (rho2_c, P2_c)
     Pot pot;        // pair c's potential (pair 0 for c = 3)
     double a[3];    // (a, b) of pairs c, c - 1, c + 1 (zeros on lane 3)
     double b[3];
     double rin2;    // pair c's squared collapse radius
+    double im;      // octet: 1/mu of the lane's side
+    double gam[3];  // octet: weights of g_AB r_AB, g_BC r_BC, g_CA r_CA in the side's force
 };
 
-QD Role make_role(const Sys& S, int c)
+QD Role make_role(const Sys& S, int c, int side = 0)
 {
     Role R;
     R.c = c;
+    R.side = side;
+    R.im = side ? S.inv_mu123 : S.inv_mu12;
+    // -dV/drho1 = -g_AB r_AB + cA g_BC r_BC + cB g_CA r_CA; -dV/drho2 = -g_BC r_BC + g_CA r_CA
+    R.gam[0] = side ? 0.0 : -1.0;
+    R.gam[1] = side ? -1.0 : S.cA;
+    R.gam[2] = side ? 1.0 : S.cB;
     for (int k = 0; k < 3; ++k) {
         const int q = c < 3 ? (k == 0 ? c : (k == 1 ? (c + 2) % 3 : (c + 1) % 3)) : -1;
         R.a[k] = q == 0 ? 1.0 : (q == 1 ? -S.cA : (q == 2 ? -S.cB : 0.0));
@@ -363,6 +374,36 @@ __device__ inline int quad_or(int v)
     return v | __builtin_amdgcn_mov_dpp(v, kDppXor2, 0xF, 0xF, true);
 }
 
+// Octets (eight lanes, two quads): DPP row shifts by four with bank masks.
+// kOctLo: lanes of the first quad (banks 0, 2) read lane + 4; kOctHi: lanes
+// of the second quad (banks 1, 3) read lane - 4; other lanes keep `old`.
+constexpr int kDppShl4 = 0x104, kDppShr4 = 0x114, kBanksLo = 0x5, kBanksHi = 0xA;
+template <int CTRL, int BANKS>
+__device__ inline double oct_update(double old, double v)
+{
+    const unsigned long long o = __builtin_bit_cast(unsigned long long, old);
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)b, CTRL, 0xF, BANKS, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL,
+                                               0xF, BANKS, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// the value of the first quad's lane in both quads
+__device__ inline double oct_from_lo(double v) { return oct_update<kDppShr4, kBanksHi>(v, v); }
+// the value of the second quad's lane in both quads
+__device__ inline double oct_from_hi(double v) { return oct_update<kDppShl4, kBanksLo>(v, v); }
+// the partner's value (lane xor 4)
+__device__ inline double oct_swap(double v)
+{
+    return oct_update<kDppShr4, kBanksHi>(oct_update<kDppShl4, kBanksLo>(v, v), v);
+}
+__device__ inline int oct_and(int v)
+{
+    const int s = __builtin_amdgcn_update_dpp(__builtin_amdgcn_update_dpp(v, v, kDppShl4, 0xF, kBanksLo, false),
+                                              v, kDppShr4, 0xF, kBanksHi, false);
+    return v & s;
+}
+
 // (s_0 + s_1) + (s_2 + s_3) over the quad, the same value in all four lanes
 __device__ inline double quad_sum(double v)
 {
@@ -383,12 +424,21 @@ template <int W, int K0, int K1, int K2>
 QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double* s2)
 {
     constexpr int NC = Lay<W>::NC;
+    // the octet gathers (rho1_c, rho2_c) in both of its quads, which then
+    // work as the quad layout does
+    double xs[2];
+    const double* xx = x;
+    if constexpr (W == 8) {
+        xs[0] = oct_from_lo(x[0]);
+        xs[1] = oct_from_hi(x[0]);
+        xx = xs;
+    }
     double rab[NC], rbc[NC], rca[NC];
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
-        rab[a] = x[a];
-        rbc[a] = fma(-S.cA, x[a], x[NC + a]);
-        rca[a] = fma(-S.cB, x[a], -x[NC + a]);
+        rab[a] = xx[a];
+        rbc[a] = fma(-S.cA, xx[a], xx[NC + a]);
+        rca[a] = fma(-S.cB, xx[a], -xx[NC + a]);
     }
     double sab = 0.0, sbc = 0.0, sca = 0.0, gab, gbc, gca;
     if constexpr (W == 1) {
@@ -407,9 +457,9 @@ QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double*
     } else {
         // component c of pairs c, c - 1, c + 1; pair p's other two
         // components gathered on lane p
-        const double u0 = fma(R.a[0], x[0], R.b[0] * x[1]);
-        const double u1 = fma(R.a[1], x[0], R.b[1] * x[1]);
-        const double u2 = fma(R.a[2], x[0], R.b[2] * x[1]);
+        const double u0 = fma(R.a[0], xx[0], R.b[0] * xx[1]);
+        const double u1 = fma(R.a[1], xx[0], R.b[1] * xx[1]);
+        const double u2 = fma(R.a[2], xx[0], R.b[2] * xx[1]);
         const double v1 = quad_perm<kDppNext>(u1);   // component p + 1 of pair p
         const double v2 = quad_perm<kDppPrev>(u2);   // component p + 2 of pair p
         const double s = fma(v2, v2, fma(v1, v1, u0 * u0));
@@ -433,13 +483,19 @@ QD void force_w(const Sys& S, const Role& R, const double* x, double* F, double*
         gbc = quad_perm<Bc<1>::ctrl>(g);
         gca = quad_perm<Bc<2>::ctrl>(g);
     }
-    const double cgbc = S.cA * gbc, cgca = S.cB * gca;
+    if constexpr (W == 8) {
+        // the side's force with per-lane weights: the same roundings as the
+        // two expressions below (a zero weight adds an exact zero)
+        F[0] = fma(R.gam[2] * gca, rca[0], fma(R.gam[1] * gbc, rbc[0], (R.gam[0] * gab) * rab[0]));
+    } else {
+        const double cgbc = S.cA * gbc, cgca = S.cB * gca;
 #pragma unroll
-    for (int a = 0; a < NC; ++a) {
-        // -dV/drho1 = -g_AB r_AB + cA g_BC r_BC + cB g_CA r_CA
-        F[a] = fma(cgca, rca[a], fma(cgbc, rbc[a], -gab * rab[a]));
-        // -dV/drho2 = -g_BC r_BC + g_CA r_CA
-        F[NC + a] = fma(gca, rca[a], -gbc * rbc[a]);
+        for (int a = 0; a < NC; ++a) {
+            // -dV/drho1 = -g_AB r_AB + cA g_BC r_BC + cB g_CA r_CA
+            F[a] = fma(cgca, rca[a], fma(cgbc, rbc[a], -gab * rab[a]));
+            // -dV/drho2 = -g_BC r_BC + g_CA r_CA
+            F[NC + a] = fma(gca, rca[a], -gbc * rbc[a]);
+        }
     }
     s2[0] = sab;
     s2[1] = sbc;
@@ -580,8 +636,11 @@ QD double comp_sum(const Role& R, const double* part)
 {
     if constexpr (W == 1) {
         return (part[0] + part[1]) + part[2];
-    } else {
+    } else if constexpr (W == 4) {
         return quad_sum(R.c < 3 ? part[0] : 0.0);
+    } else {
+        // the second quad holds the complete per-component sums
+        return oct_from_hi(quad_sum(R.c < 3 ? part[0] : 0.0));
     }
 }
 
@@ -595,15 +654,16 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
                        double* pn, double* F7, double* s2)
 {
     using namespace dp;
-    constexpr int NC = Lay<W>::NC, N = 2 * NC;
+    constexpr int NC = Lay<W>::NC, N = Lay<W>::N;
     kcoef_t* K = dp_coefs();
     double X[N], F2[N], F3[N], F4[N], F5[N], F6[N], junk[3];
     const double hh = h * h;
     // per-component 1/mu (uniform) and h^2/mu
     const double im0 = S.inv_mu12, im1 = S.inv_mu123;
     const double g0 = hh * im0, g1 = hh * im1;
-#define IM(i) ((i) < NC ? im0 : im1)
-#define GG(i) ((i) < NC ? g0 : g1)
+    const double gR = hh * R.im;   // octet: the lane's side
+#define IM(i) (W == 8 ? R.im : ((i) < NC ? im0 : im1))
+#define GG(i) (W == 8 ? gR : ((i) < NC ? g0 : g1))
     // h v = h p / mu, formed once per step for the stage positions
     double hv[N];
 #pragma unroll
@@ -646,19 +706,30 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
 #undef GG
     force_w<W, K0, K1, K2>(S, R, xn, F7, s2);
     double part[NC];
+    if constexpr (W == 8) {
+        // the lane holds the k = side terms: the second quad continues the
+        // first quad's partial sum of its component
+        const double epi = fma(K[E7], F7[0], ep[0]);
+        const double sx = fma(rtol, fmax(fabs(x[0]), fabs(xn[0])), atol);
+        const double sp = fma(rtol, fmax(fabs(p[0]), fabs(pn[0])), atol);
+        const double qx = ex[0] * rcp_norm(sx), qp = epi * (h * rcp_norm(sp));
+        const double lo = oct_from_lo(fma(qx, qx, qp * qp));
+        part[0] = fma(qx, qx, fma(qp, qp, lo));
+    } else {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double acc = 0.0;
+        for (int c = 0; c < NC; ++c) {
+            double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int i = c + k * NC;
-            const double epi = fma(K[E7], F7[i], ep[i]);
-            const double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
-            const double sp = fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol);
-            const double qx = ex[i] * rcp_norm(sx), qp = epi * (h * rcp_norm(sp));
-            acc = fma(qx, qx, mac(k == 0, qp, qp, acc));
+            for (int k = 0; k < 2; ++k) {
+                const int i = c + k * NC;
+                const double epi = fma(K[E7], F7[i], ep[i]);
+                const double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
+                const double sp = fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol);
+                const double qx = ex[i] * rcp_norm(sx), qp = epi * (h * rcp_norm(sp));
+                acc = fma(qx, qx, mac(k == 0, qp, qp, acc));
+            }
+            part[c] = acc;
         }
-        part[c] = acc;
     }
     const double m = comp_sum<W>(R, part) * (1.0 / 12.0);
     double d, id;
@@ -787,14 +858,15 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
                        double* pn, double* F13, double* s2)
 {
     using namespace d8;
-    constexpr int NC = Lay<W>::NC, N = 2 * NC;
+    constexpr int NC = Lay<W>::NC, N = Lay<W>::N;
     kcoef_t* K = d8_coefs();
     double F[NS][N], junk[3];
     const double hh = h * h;
     const double im0 = S.inv_mu12, im1 = S.inv_mu123;
     const double g0 = hh * im0, g1 = hh * im1;
-#define IM(i) ((i) < NC ? im0 : im1)
-#define GG(i) ((i) < NC ? g0 : g1)
+    const double gR = hh * R.im;   // octet: the lane's side
+#define IM(i) (W == 8 ? R.im : ((i) < NC ? im0 : im1))
+#define GG(i) (W == 8 ? gR : ((i) < NC ? g0 : g1))
 #pragma unroll
     for (int i = 0; i < N; ++i) F[0][i] = F1[i];
     // h v = h p / mu, formed once per step for the stage positions
@@ -854,7 +926,7 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
     for (int c = 0; c < NC; ++c) {
         double n5 = 0.0, n3 = 0.0;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < (W == 8 ? 1 : 2); ++k) {
             const int i = c + k * NC;
             // (the h of the momentum errors folded into their weight)
             const double e5p = fma(K[IX.e5_13], F13[i], ep5[i]);
@@ -862,8 +934,17 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
             const double isx = rcp_norm(fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol));
             const double isp = h * rcp_norm(fma(rtol, fmax(fabs(p[i]), fabs(pn[i])), atol));
             const double a = ex5[i] * isx, b = e5p * isp, cc = ex3[i] * isx, d = e3p * isp;
-            n5 = fma(a, a, mac(k == 0, b, b, n5));
-            n3 = fma(cc, cc, mac(k == 0, d, d, n3));
+            if constexpr (W == 8) {
+                // the lane holds the k = side terms: the second quad continues
+                // the first quad's partial sums of its component
+                const double lo5 = oct_from_lo(fma(a, a, b * b));
+                const double lo3 = oct_from_lo(fma(cc, cc, d * d));
+                n5 = fma(a, a, fma(b, b, lo5));
+                n3 = fma(cc, cc, fma(d, d, lo3));
+            } else {
+                n5 = fma(a, a, mac(k == 0, b, b, n5));
+                n3 = fma(cc, cc, mac(k == 0, d, d, n3));
+            }
         }
         part5[c] = n5;
         part3[c] = n3;
@@ -918,7 +999,7 @@ QD double initial_step(const Sys& S, const double* x, const double* p, const dou
 // ---------------------------------------------------------------------------
 template <int W>
 struct LaneW {
-    double x[2 * Lay<W>::NC], p[2 * Lay<W>::NC], F[2 * Lay<W>::NC];
+    double x[Lay<W>::N], p[Lay<W>::N], F[Lay<W>::N];
     double t, tmax, rstop2, h;
     int32_t nstep, nrej, status, last_rej;
 };
@@ -935,7 +1016,7 @@ using Lane = LaneW<1>;
 template <int W, int K0, int K1, int K2, int RK = 0>
 QD void lane_step_w(const Sys& S, const Role& R, const Prm& P, LaneW<W>& L)
 {
-    constexpr int N = 2 * Lay<W>::NC;
+    constexpr int N = Lay<W>::N;
     double xn[N], pn[N], Fn[N], s2[3];
     const double span = L.tmax - L.t;
     const double hs = fmin(L.h, span);
@@ -959,8 +1040,9 @@ QD void lane_step_w(const Sys& S, const Role& R, const Prm& P, LaneW<W>& L)
     }
     bool finite = z == 0.0;
     bool collapsed, far;
-    if constexpr (W == 4) {
-        finite = quad_and(finite ? 1 : 0) != 0;
+    if constexpr (W >= 4) {
+        const int f = quad_and(finite ? 1 : 0);
+        finite = (W == 8 ? oct_and(f) : f) != 0;
         // each lane tests its own pair; lane 3 has none
         const int own = R.c < 3 ? ((s2[0] < R.rin2 ? 1 : 0) | (s2[0] > L.rstop2 ? 2 : 0)) : 0;
         const int any = quad_or(own);

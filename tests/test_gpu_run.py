@@ -63,7 +63,7 @@ def test_run_is_schedule_independent(Q, torch, rk):
     ref = None
     for blocks, rm, ce, lpt, lanes in [(0, 1, 1, 1, 4), (3, 1, 1, 1, 1), (5, 64, 1, 0, 4),
                                        (2, 8, 7, 1, 1), (1, 1, 3, 0, 4), (7, 3, 2, 1, 4),
-                                       (0, 1, 8, 1, 1)]:
+                                       (0, 1, 8, 1, 1), (2, 8, 5, 1, 8), (0, 1, 1, 0, 8)]:
         o = Q.RunOpts(blocks=blocks, refill_min=rm, check_every=ce, lpt=lpt, graph=0, rk=rk,
                       lanes=lanes)
         ctx.run(buf, o)
@@ -139,19 +139,20 @@ def _system_cases():
 @pytest.mark.parametrize("case", ["all_morse", "lj_morse_buck", "generic", "buck_collapse"])
 @pytest.mark.parametrize("rk", [1, 2], ids=["dopri5", "dop853"])
 def test_quad_lanes_equal_single_lane(Q, torch, case, rk):
-    """The quad layout (four lanes per trajectory, DPP exchanges) gives the
-    same bits as one lane per trajectory, for every kernel specialisation
-    and both RK variants."""
+    """The quad and octet layouts (four or eight lanes per trajectory, DPP
+    exchanges) give the same bits as one lane per trajectory, for every
+    kernel specialisation and both RK variants."""
     system, inst = _system_cases()[case]
     ctx = Q.Context(system, W.Params())
     ctx.set_instances(inst)
     buf = ctx.new_run_buffers()
     snaps = []
-    for lanes in (1, 4):
+    for lanes in (1, 4, 8):
         ctx.run(buf, Q.RunOpts(refill_min=1, check_every=4, lpt=1, graph=0, rk=rk, lanes=lanes))
         torch.cuda.synchronize()
         snaps.append(_snapshot(buf))
     _same(snaps[0], snaps[1])
+    _same(snaps[0], snaps[2])
     assert np.all(snaps[0]["status"] != Q.RUNNING)
     if case == "buck_collapse":
         assert np.any(snaps[0]["status"] == Q.COLLAPSE)
@@ -187,7 +188,7 @@ def test_autotune_returns_valid_options(Q, torch, search_rk):
     best, ms = ctx.autotune(buf, reps=1, search_rk=search_rk, energy_gate=1e-8)
     assert ms > 0 and best.blocks > 0 and 1 <= best.refill_min <= 64 and best.check_every >= 1
     assert best.rk in ((1, 2) if search_rk else (0,))
-    assert best.lanes in (1, 4)
+    assert best.lanes in (1, 4, 8)
     ctx.run(buf, Q.RunOpts(graph=0, refill_min=1, check_every=1, lpt=1, rk=best.rk))
     torch.cuda.synchronize()
     ref = _snapshot(buf)
@@ -213,7 +214,7 @@ def test_autotune_cache(Q, torch):
     b2, ms2 = ctx2.autotune(buf2, reps=1)
     assert b1.as_dict() == b2.as_dict() and ms1 == ms2
     b3, ms3 = ctx2.autotune(buf2, reps=1, retune=True)
-    assert ms3 != ms1 and b3.lanes in (1, 4)
+    assert ms3 != ms1 and b3.lanes in (1, 4, 8)
     b4, ms4 = ctx.autotune(buf, reps=1)
     assert b4.as_dict() == b3.as_dict() and ms4 == ms3
 
