@@ -35,7 +35,7 @@ F_STEP = {("morse", 0): 1833.7, ("morse", 1): 3996.7,
 # HBM bytes per launch of the persistent kernel from FETCH_SIZE and WRITE_SIZE
 # passes scaled by a streaming kernel of known size, for the kernel as it was
 # when the counters were taken (workload, kernel) -> bytes; null otherwise.
-TRAFFIC = {("batched", "k_persistent<4,0,0,0,1>"): 134.53e6}
+TRAFFIC = {("batched", "k_persistent<4,0,0,0,1>"): 134.38e6}
 RK_NAMES = {"dopri5": 0, "dop853": 1}
 KINDS = {"morse": "0,0,0", "mixed": "3,0,2"}   # 3: LJ 12-6 specialisation
 # workload -> (surface, default CPU-baseline stride)
@@ -193,6 +193,13 @@ def main():
     trial_steps = int(per_traj.sum())
     f_step = F_STEP[(surface, rk)]
     achieved = trial_steps * f_step / (prop_ms * 1e-3) / 1e12 if f_step else None
+    slots = None
+    if args.path == "run":
+        # how full the persistent waves' slots were over their trial-step loop
+        wave_steps = ctx.last_run_wave_steps()
+        spw = 64 // used.lanes
+        slots = {"wave_steps": wave_steps, "slots_per_wave": spw,
+                 "slot_utilization": trial_steps / (wave_steps * spw) if wave_steps else None}
     lab = out.label.cpu().numpy()
     dE = out.d[3].cpu().numpy()
     fin = lab != Q.FAILED
@@ -223,6 +230,7 @@ def main():
                      "timed_ms": prop_ms, "trial_steps": trial_steps,
                      "flop_per_trial_step": f_step},
         "path": args.path, "run_opts": used.as_dict() if used else opts.as_dict(),
+        "slots": slots,
         "autotune": tuned,
         "trial_steps_per_s": trial_steps / (ms_step * 1e-3),
         "trial_steps_per_traj": {q: int(np.percentile(per_traj, p)) for q, p in

@@ -322,6 +322,14 @@ int qcams_run(qcams_ctx *ctx, const qcams_run_opts *opts, const qcams_state *st,
  * run to finish.  sync.  Errors: EINVAL (no run yet), EHIP. */
 int qcams_last_run_kernel_ms(qcams_ctx *ctx, double *ms);
 
+/* Iterations of the trial-step loop that the persistent waves of the last
+ * qcams_run executed with at least one slot stepping (each such iteration
+ * steps every running slot of its wave once).  Divided into the run's trial
+ * steps (sum of nstep + nrej) it gives the slot utilisation, with
+ * 64 / lanes slots per wave.  Waits for the run.  sync.  Errors: EINVAL (no
+ * run yet), EHIP. */
+int qcams_last_run_wave_steps(qcams_ctx *ctx, int64_t *wave_steps);
+
 /* The options the last qcams_run on this context took effect with: blocks,
  * refill_min and check_every as clamped, rk = 1 (DOPRI5) or 2 (DOP853),
  * lanes = 1, 4 or 8.  host only.  Errors: EINVAL (no run yet). */

@@ -41,7 +41,7 @@ struct qcams_ctx {
     int32_t* d_lpt_inst = nullptr;   // [n_inst] instance index by LPT rank
     int64_t* d_lpt_off = nullptr;    // [n_inst + 1] work offsets in LPT order
     int64_t* d_nat_off = nullptr;    // [n_inst + 1] natural (id-sorted) offsets
-    unsigned long long* d_counter = nullptr;   // work counter of the persistent run
+    unsigned long long* d_counter = nullptr;   // [0] work counter, [1] wave-steps of the persistent run
     int64_t* d_order = nullptr;                // [n_total] work item -> natural position
     int64_t order_cap = 0;
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
@@ -340,7 +340,11 @@ __global__ void __launch_bounds__(256) k_record(Sys S, Prm P, double* d, int32_t
 // to the same natural position (instances in id order), where classification
 // and reduction read them.
 // ---------------------------------------------------------------------------
-__global__ void k_reset_counter(unsigned long long* c) { *c = 0ull; }
+__global__ void k_reset_counter(unsigned long long* c)
+{
+    c[0] = 0ull;
+    c[1] = 0ull;
+}
 
 struct RunMap {
     const int64_t* order;   // work item -> natural position
@@ -449,6 +453,7 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
     int64_t pos = -1;
     bool active = false;
     bool exhausted = false;
+    unsigned wsteps = 0;   // iterations in which the wave stepped any slot
     L.status = RUNNING;
     for (;;) {
         // ---- refill (wave-uniform) ----
@@ -495,8 +500,18 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
         }
         if (__ballot(active) == 0ull) break;
         // ---- integrate ----
+        const int32_t trials0 = L.nstep + L.nrej;
         for (int s = 0; s < check_every; ++s) {
             if (active && L.status == RUNNING) lane_step_w<W, K0, K1, K2, RK>(S, R, P, L);
+        }
+        // a slot that stops stays stopped until the retirement below, so the
+        // iterations in which the wave stepped any slot are the most trials
+        // one slot made; nearly always some slot made all of them
+        {
+            const int32_t ran = L.nstep + L.nrej - trials0;
+            int k = check_every;
+            while (k > 0 && __ballot(ran >= k) == 0ull) --k;
+            wsteps += (unsigned)k;
         }
         // ---- retire finished trajectories ----
         if (active && L.status != RUNNING) {
@@ -516,6 +531,7 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
             L.status = RUNNING;
         }
     }
+    if (lane == 0) atomicAdd(&counter[1], (unsigned long long)wsteps);
 }
 
 // ---------------------------------------------------------------------------
@@ -1490,7 +1506,7 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
             return fail(c, QCAMS_EINVAL, "proposal instances need a sample buffer and a proposal");
     HIP_OK(c, hipSetDevice(c->device));
     if (!c->d_counter) {
-        if (hipMalloc(&c->d_counter, sizeof(unsigned long long)) != hipSuccess) {
+        if (hipMalloc(&c->d_counter, 2 * sizeof(unsigned long long)) != hipSuccess) {
             c->d_counter = nullptr;
             return fail(c, QCAMS_ENOMEM, "work counter allocation failed");
         }
@@ -1762,6 +1778,18 @@ int qcams_last_run_options(qcams_ctx* c, qcams_run_opts* used)
     if (!c || !used) return fail(c, QCAMS_EINVAL, "null argument");
     if (!c->has_run) return fail(c, QCAMS_EINVAL, "no run recorded");
     *used = c->last_opts;
+    return QCAMS_OK;
+}
+
+int qcams_last_run_wave_steps(qcams_ctx* c, int64_t* wave_steps)
+{
+    if (!c || !wave_steps) return fail(c, QCAMS_EINVAL, "null argument");
+    if (!c->has_run || !c->d_counter) return fail(c, QCAMS_EINVAL, "no run recorded");
+    HIP_OK(c, hipSetDevice(c->device));
+    HIP_OK(c, hipEventSynchronize(c->ev_prop[1]));
+    unsigned long long v = 0;
+    HIP_OK(c, hipMemcpy(&v, c->d_counter + 1, sizeof v, hipMemcpyDeviceToHost));
+    *wave_steps = (int64_t)v;
     return QCAMS_OK;
 }
 

@@ -122,6 +122,7 @@ def lib():
     L.qcams_run.argtypes = [vp, C.POINTER(RunOpts), C.POINTER(StateC), vp, C.POINTER(OutcomeC),
                             vp, vp, vp, vp]
     L.qcams_last_run_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
+    L.qcams_last_run_wave_steps.argtypes = [vp, C.POINTER(C.c_int64)]
     L.qcams_last_run_options.argtypes = [vp, C.POINTER(RunOpts)]
     L.qcams_grid_groups.argtypes = [vp, C.POINTER(C.c_int32), vp]
     L.qcams_dvr_levels.argtypes = [vp, i32, C.c_double, C.c_double, i32, vp, vp, vp]
@@ -391,6 +392,13 @@ class Context:
         ms = C.c_double()
         self._check(lib().qcams_last_run_kernel_ms(self._h, C.byref(ms)), "qcams_last_run_kernel_ms")
         return ms.value
+
+    def last_run_wave_steps(self) -> int:
+        """Trial-step loop iterations the persistent waves of the last run
+        executed with at least one slot stepping."""
+        v = C.c_int64()
+        self._check(lib().qcams_last_run_wave_steps(self._h, C.byref(v)), "qcams_last_run_wave_steps")
+        return v.value
 
     def propagate_record(self, st: State, rec_max: int, n: Optional[int] = None, stream=None):
         """qcams_propagate recording (t, r_AB, r_BC, r_CA) after every accepted

@@ -69,6 +69,12 @@ def test_run_is_schedule_independent(Q, torch, rk):
         ctx.run(buf, o)
         torch.cuda.synchronize()
         snap = _snapshot(buf)
+        # every counted loop iteration steps between one and all slots of
+        # its wave, and a trajectory's trials fall in distinct iterations
+        trials = snap["nstep"].astype(np.int64) + snap["nrej"]
+        ws = ctx.last_run_wave_steps()
+        assert trials.sum() <= ws * (64 // lanes) and ws <= trials.sum(), (ws, trials.sum())
+        assert ws >= trials.max()
         if ref is None:
             ref = snap
             # ids at natural positions: instances in id order, consecutive ids
