@@ -447,7 +447,7 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
     const unsigned lane = __lane_id();
     const int c = W == 1 ? 0 : (int)(lane & 3u);
     const int side = W == 8 ? (int)((lane >> 2) & 1u) : 0;
-    const Role R = make_role(S, c, side);
+    const Role R = with_table<RK>(make_role(S, c, side));
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     LaneW<W> L;
     int64_t pos = -1;

@@ -300,6 +300,14 @@ template <> struct Lay<1> { static constexpr int NC = 3, N = 6; };
 template <> struct Lay<4> { static constexpr int NC = 1, N = 2; };
 template <> struct Lay<8> { static constexpr int NC = 1, N = 1; };
 
+// RK coefficient tables live in constant memory (address space 4 on the
+// device, read with scalar loads).
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef __attribute__((address_space(4))) const double kcoef_t;
+#else
+typedef const double kcoef_t;
+#endif
+
 // A lane's part in its quad (W = 4 only).  Component c of pair q is
 // fma(a_q, rho1_c, b_q rho2_c) with (a, b) = (1, 0), (-cA, 1), (-cB, -1) for
 // AB, BC, CA (b rho2 is exact, so this rounds as the one-lane expressions).
@@ -312,6 +320,7 @@ struct Role {
     double rin2;    // pair c's squared collapse radius
     double im;      // octet: 1/mu of the lane's side
     double gam[3];  // octet: weights of g_AB r_AB, g_BC r_BC, g_CA r_CA in the side's force
+    kcoef_t* kt;    // coefficient table of the step's RK variant
 };
 
 QD Role make_role(const Sys& S, int c, int side = 0)
@@ -588,11 +597,6 @@ constexpr double z6 = e7 * b6;
 // scalar registers and spill.  Each table lists the nonzero coefficients in
 // the order the step uses them, so consecutive reads merge.
 // ---------------------------------------------------------------------------
-#if defined(__HIP_DEVICE_COMPILE__)
-typedef __attribute__((address_space(4))) const double kcoef_t;
-#else
-typedef const double kcoef_t;
-#endif
 
 namespace dp {
 enum : int {
@@ -611,15 +615,14 @@ constexpr Vals VALS = vals();
 }  // namespace dp
 static __constant__ dp::Vals kDp = dp::vals();
 
-QD kcoef_t* dp_coefs()
+// The table pointer, opaque to the compiler from here on: the coefficients
+// are read afresh in every step instead of being hoisted out of the step loop.
+QD kcoef_t* opaque_table(kcoef_t* k)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    kcoef_t* k = (kcoef_t*)&kDp.v[0];
     asm volatile("" : "+s"(k));
-    return k;
-#else
-    return &dp::VALS.v[0];
 #endif
+    return k;
 }
 
 // acc + a b, or a b alone for the first term of a sum (a product, not an
@@ -655,7 +658,7 @@ QD double dopri5_trial(const Sys& S, const Role& R, const double* x, const doubl
 {
     using namespace dp;
     constexpr int NC = Lay<W>::NC, N = Lay<W>::N;
-    kcoef_t* K = dp_coefs();
+    kcoef_t* K = opaque_table(R.kt);
     double X[N], F2[N], F3[N], F4[N], F5[N], F6[N], junk[3];
     const double hh = h * h;
     // per-component 1/mu (uniform) and h^2/mu
@@ -841,15 +844,27 @@ constexpr Vals VALS = vals();
 }  // namespace d8
 static __constant__ d8::Vals kD8 = d8::vals();
 
-QD kcoef_t* d8_coefs()
+// The coefficient table of RK variant RK (1: DOP853, else DOPRI5).  Taken
+// once per kernel and kept in scalar registers, so a step does not fetch the
+// table's address again.
+template <int RK>
+QD kcoef_t* coef_table()
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    kcoef_t* k = (kcoef_t*)&kD8.v[0];
-    asm volatile("" : "+s"(k));
-    return k;
+    return RK == 1 ? (kcoef_t*)&kD8.v[0] : (kcoef_t*)&kDp.v[0];
 #else
-    return &d8::VALS.v[0];
+    return RK == 1 ? &d8::VALS.v[0] : &dp::VALS.v[0];
 #endif
+}
+
+template <int RK>
+QD Role with_table(Role R)
+{
+    R.kt = coef_table<RK>();
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+s"(R.kt));
+#endif
+    return R;
 }
 
 template <int W, int K0, int K1, int K2>
@@ -859,7 +874,7 @@ QD double dop853_trial(const Sys& S, const Role& R, const double* x, const doubl
 {
     using namespace d8;
     constexpr int NC = Lay<W>::NC, N = Lay<W>::N;
-    kcoef_t* K = d8_coefs();
+    kcoef_t* K = opaque_table(R.kt);
     double F[NS][N], junk[3];
     const double hh = h * h;
     const double im0 = S.inv_mu12, im1 = S.inv_mu123;
@@ -1082,7 +1097,7 @@ QD void lane_step_w(const Sys& S, const Role& R, const Prm& P, LaneW<W>& L)
 template <int K0, int K1, int K2, int RK = 0>
 QD void lane_step(const Sys& S, const Prm& P, Lane& L)
 {
-    lane_step_w<1, K0, K1, K2, RK>(S, Role{}, P, L);
+    lane_step_w<1, K0, K1, K2, RK>(S, with_table<RK>(Role{}), P, L);
 }
 
 // ---------------------------------------------------------------------------

@@ -3,7 +3,9 @@ are a pure function of the trajectory id whatever the schedule (grid size,
 refill threshold, check interval, instance order, one lane or a quad of
 lanes per trajectory); graph replays equal the eager run; the autotuner
 returns a valid option set; cross sections agree with the oracle within 3
-combined standard errors; the run equals the unfused ABI path."""
+combined standard errors; the run equals the unfused ABI path; the batched,
+mixed-potential and sweep workloads at full size in the benchmark's launch
+configuration."""
 import math
 
 import numpy as np
@@ -321,3 +323,92 @@ def test_full_size_bench_configuration(Q, torch, orc):
             assert pv > 1e-4, (ch, k, xs[k, 7 + ch], ko, int(m[k]), pv)
     print("pooled P gpu", xs[:, 7:11].mean(axis=0), "oracle subsample",
           (ref["P"] * m[:, None]).sum(axis=0) / m.sum())
+
+
+def _full_size_run(Q, torch, orc, wl, n_expect, seed):
+    """One fused run of a whole workload in the benchmark's launch
+    configuration and at its tolerances, then the checks that need no
+    per-trajectory oracle integration: every trajectory finished, counts per
+    instance, the energy gate, and 48 sampled trajectories one by one (initial
+    draws bit-exact; the classification of the GPU's own final state
+    bit-exact).  Returns the labels, ids and per-instance results."""
+    wl.params = W.gated_params(wl, W.RK_DOP853)
+    ctx = Q.Context(wl.system, wl.params)
+    ctx.set_instances(wl.instances)
+    buf = ctx.new_run_buffers()
+    ctx.run(buf, Q.RunOpts(graph=1, refill_min=1, check_every=8, lpt=1))
+    torch.cuda.synchronize()
+    used = ctx.last_run_options()
+    st, out = buf["state"], buf["outcome"]
+    n = buf["ids"].numel()
+    assert n == n_expect
+    assert used.rk == 2 and used.blocks > 0 and used.lanes in (1, 4, 8)
+    assert not bool((st.status == Q.RUNNING).any())
+    lab = out.label.cpu().numpy()
+    ids = buf["ids"].cpu().numpy()
+    xs = buf["xs"].cpu().numpy()
+    assert np.array_equal(xs[:, 0], [I.n_traj for I in wl.instances])
+    assert np.array_equal(xs[:, 1:7].sum(axis=1), xs[:, 0])
+    fin = lab != Q.FAILED
+    assert fin.mean() > 0.999
+    dE = out.d[3].cpu().numpy()
+    assert np.abs(dE[fin]).max() < 1e-8, float(np.abs(dE[fin]).max())
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(n, 48, replace=False))
+    tp = torch.as_tensor(pick, device=buf["ids"].device)
+    smp = buf["sample"][:, tp].cpu().numpy()
+    dfin = st.d[:12][:, tp].cpu().numpy()
+    vt, jt = out.vt[tp].cpu().numpy(), out.jt[tp].cpu().numpy()
+    sys, prm = orc.make_system(wl.system), orc.make_params(wl.params)
+    firsts = np.array([I.first_id for I in wl.instances])
+    which = np.searchsorted(firsts, ids, side="right") - 1
+    for k, c in enumerate(pick):
+        I = wl.instances[which[c]]
+        lev = orc.level(sys, I.v, I.j)
+        _, _, sm = orc.init(sys, prm, orc.make_instance(I), lev, int(ids[c]))
+        assert np.array_equal(smp[:5, k], sm[:5]), c
+        if fin[c]:
+            cl = orc.classify(sys, prm, dfin[:, k])
+            assert (cl["label"], cl["vt"], cl["jt"]) == (lab[c], vt[k], jt[k]), c
+    return lab, ids, xs
+
+
+def _pooled_channels_vs_oracle(orc, wl, xs, n, per):
+    """Per-channel probabilities pooled over instances (every instance holds
+    the same number of trajectories, so the pooled value is the mean of the
+    per-instance ones): the GPU's full run against the oracle's on a
+    stratified subsample, within 3 combined standard errors."""
+    recs, w2 = orc.run_workload(wl, per, processes=8)
+    ref = orc.cross_sections(wl, recs["label"], np.ones(len(recs)), w2)
+    m = np.array([len(p) for p in per])
+    for ch in range(4):
+        p_g = xs[:, 7 + ch].mean()
+        p_o = (ref["P"][:, ch] * m).sum() / m.sum()
+        se = math.sqrt(max(p_g * (1 - p_g), 1e-12) / n + max(p_o * (1 - p_o), 1e-12) / m.sum())
+        assert abs(p_g - p_o) <= 3 * se, (ch, p_g, p_o, se)
+    print("pooled P gpu", xs[:, 7:11].mean(axis=0), "oracle subsample",
+          (ref["P"] * m[:, None]).sum(axis=0) / m.sum(), "oracle trajectories", m.sum())
+
+
+def test_full_size_mixed_configuration(Q, torch, orc):
+    """The 1,001,088-trajectory mixed-potential workload (generalized LJ 12-6,
+    Morse, Buckingham; 2112 instances) at full size in the benchmark's launch
+    configuration: the checks of _full_size_run, then pooled channel
+    probabilities against the oracle on one id from every instance."""
+    wl = W.config_mixed()
+    lab, ids, xs = _full_size_run(Q, torch, orc, wl, 1001088, seed=11)
+    per = [np.array([I.first_id + (k * 37) % I.n_traj], dtype=np.int64)
+           for k, I in enumerate(wl.instances)]
+    _pooled_channels_vs_oracle(orc, wl, xs, len(ids), per)
+
+
+def test_full_size_sweep_configuration(Q, torch, orc):
+    """The 10,005,248-trajectory sweep (64 collision energies x v 0-10 x
+    j 0-10, 7744 instances) at full size in the benchmark's launch
+    configuration: the checks of _full_size_run, then pooled channel
+    probabilities against the oracle on one id from every instance."""
+    wl = W.config_sweep()
+    lab, ids, xs = _full_size_run(Q, torch, orc, wl, 10005248, seed=13)
+    per = [np.array([I.first_id + (k * 53) % I.n_traj], dtype=np.int64)
+           for k, I in enumerate(wl.instances)]
+    _pooled_channels_vs_oracle(orc, wl, xs, len(ids), per)
