@@ -41,7 +41,7 @@ struct qcams_ctx {
     int32_t* d_lpt_inst = nullptr;   // [n_inst] instance index by LPT rank
     int64_t* d_lpt_off = nullptr;    // [n_inst + 1] work offsets in LPT order
     int64_t* d_nat_off = nullptr;    // [n_inst + 1] natural (id-sorted) offsets
-    unsigned long long* d_counter = nullptr;   // [0] work counter, [1] wave-steps of the persistent run
+    unsigned long long* d_counter = nullptr;   // [kCounters] of the persistent run: work cursors, wave steps
     int64_t* d_order = nullptr;                // [n_total] work item -> natural position
     int64_t order_cap = 0;
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
@@ -340,16 +340,39 @@ __global__ void __launch_bounds__(256) k_record(Sys S, Prm P, double* d, int32_t
 // to the same natural position (instances in id order), where classification
 // and reduction read them.
 // ---------------------------------------------------------------------------
+// Work of the persistent run, XCD by XCD.  Each XCD (its own L2) has a list
+// of its own: the work order cut into chunks of kChunk consecutive items,
+// chunk k on list k mod kLists.  Consecutive items of an instance sit at
+// consecutive natural positions, so the cache lines of a chunk's state rows
+// are read and written by one XCD only.  A wave takes work from its XCD's
+// list first and from the next lists once that one is used up.
+constexpr int kChunk = 16;    // items per chunk: one 128-byte line of a state row
+constexpr int kLists = 8;     // XCDs of the MI355X
+constexpr int kWaveSteps = kLists;   // counter slot of the wave-step count
+constexpr int kCounters = kLists + 1;
+
 __global__ void k_reset_counter(unsigned long long* c)
 {
-    c[0] = 0ull;
-    c[1] = 0ull;
+    if (threadIdx.x < kCounters) c[threadIdx.x] = 0ull;
 }
 
 struct RunMap {
     const int64_t* order;   // work item -> natural position
     int64_t N;
 };
+
+// length of list x, and its j-th work item
+__device__ inline int64_t list_len(int64_t N, int x)
+{
+    const int64_t full = N / (kChunk * kLists), rem = N % (kChunk * kLists);
+    const int64_t tail = rem - (int64_t)x * kChunk;
+    return full * kChunk + (tail < 0 ? 0 : (tail > kChunk ? kChunk : tail));
+}
+
+__device__ inline int64_t list_item(int64_t j, int x)
+{
+    return ((j / kChunk) * kLists + x) * kChunk + (j % kChunk);
+}
 
 // natural positions and ids of the installed instances, and the work order
 // (instances longest-expected-first, or in id order)
@@ -452,24 +475,31 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
     LaneW<W> L;
     int64_t pos = -1;
     bool active = false;
-    bool exhausted = false;
     unsigned wsteps = 0;   // iterations in which the wave stepped any slot
+    int lists_left = kLists;   // work lists this wave has not found used up
     L.status = RUNNING;
     for (;;) {
         // ---- refill (wave-uniform) ----
         const unsigned long long idle = __ballot(!active);
         const int nidle = __popcll(idle) / W;
         const bool none_active = nidle == SLOTS;
-        if (!exhausted && (nidle >= refill_min || (none_active && nidle > 0))) {
+        // one grab per refill from the current list; slots it leaves idle
+        // (the list ran out) are filled from the next list on the next pass
+        if (lists_left > 0 && nidle > 0 && (nidle >= refill_min || none_active)) {
+            // the wave's XCD: hardware register XCC_ID, bits 3:0
+            const int xcd = (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kLists - 1));
+            const int x = (xcd + kLists - lists_left) & (kLists - 1);
             unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(counter, (unsigned long long)nidle);
+            if (lane == 0) base = atomicAdd(&counter[x], (unsigned long long)nidle);
             const unsigned lo32 = __builtin_amdgcn_readfirstlane((unsigned)(base & 0xffffffffull));
             const unsigned hi32 = __builtin_amdgcn_readfirstlane((unsigned)(base >> 32));
             base = ((unsigned long long)hi32 << 32) | lo32;
-            if (base + (unsigned long long)nidle >= (unsigned long long)M.N) exhausted = true;
-            if (!active) {
-                const int64_t w = (int64_t)base + __popcll(idle & lt_mask) / W;
-                if (w < M.N) {
+            const int64_t left = list_len(M.N, x) - (int64_t)base;
+            if (left < nidle) --lists_left;
+            const int rank = __popcll(idle & lt_mask) / W;   // among the idle slots
+            if (!active && rank < left) {
+                const int64_t w = list_item((int64_t)base + rank, x);
+                {
                     // row addresses formed here, not hoisted out of the loop
                     // (they would hold scalar registers across the steps)
                     const double* dr = d;
@@ -498,7 +528,10 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
                 }
             }
         }
-        if (__ballot(active) == 0ull) break;
+        if (__ballot(active) == 0ull) {
+            if (lists_left == 0) break;
+            continue;   // every slot idle: take from the next list at once
+        }
         // ---- integrate ----
         const int32_t trials0 = L.nstep + L.nrej;
         for (int s = 0; s < check_every; ++s) {
@@ -531,7 +564,7 @@ k_persistent(Sys S, Prm P, RunMap M, unsigned long long* counter, int refill_min
             L.status = RUNNING;
         }
     }
-    if (lane == 0) atomicAdd(&counter[1], (unsigned long long)wsteps);
+    if (lane == 0) atomicAdd(&counter[kWaveSteps], (unsigned long long)wsteps);
 }
 
 // ---------------------------------------------------------------------------
@@ -1429,7 +1462,7 @@ static void enqueue_pre(qcams_ctx* c, const qcams_run_opts* o, const qcams_state
                        lpt ? c->d_lpt_inst : c->d_id_inst, lpt ? c->d_lpt_off : c->d_nat_off,
                        c->d_nat_off, n, ids, c->d_order);
     dispatch_init(c, run_variant(c, o), ids, n, st, sample, s);
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, c->d_counter);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, c->d_counter);
 }
 
 static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const qcams_state* st,
@@ -1506,7 +1539,7 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
             return fail(c, QCAMS_EINVAL, "proposal instances need a sample buffer and a proposal");
     HIP_OK(c, hipSetDevice(c->device));
     if (!c->d_counter) {
-        if (hipMalloc(&c->d_counter, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        if (hipMalloc(&c->d_counter, kCounters * sizeof(unsigned long long)) != hipSuccess) {
             c->d_counter = nullptr;
             return fail(c, QCAMS_ENOMEM, "work counter allocation failed");
         }
@@ -1788,7 +1821,7 @@ int qcams_last_run_wave_steps(qcams_ctx* c, int64_t* wave_steps)
     HIP_OK(c, hipSetDevice(c->device));
     HIP_OK(c, hipEventSynchronize(c->ev_prop[1]));
     unsigned long long v = 0;
-    HIP_OK(c, hipMemcpy(&v, c->d_counter + 1, sizeof v, hipMemcpyDeviceToHost));
+    HIP_OK(c, hipMemcpy(&v, c->d_counter + kWaveSteps, sizeof v, hipMemcpyDeviceToHost));
     *wave_steps = (int64_t)v;
     return QCAMS_OK;
 }
