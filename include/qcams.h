@@ -306,7 +306,10 @@ typedef struct {
  * ids[p] (device int64 [N], written) as the matching trajectory id.  xs,
  * hist (may be NULL) as in qcams_cross_sections.  opts may be NULL
  * (defaults: 1 workgroup per CU, refill_min 1, check_every 8, LPT, no
- * graph, the context's RK variant, lanes chosen by run size).  Per-trajectory
+ * graph, the context's RK variant, lanes chosen by run size).  The work
+ * order (LPT or natural) is dealt to the 8 XCDs in chunks of 16 items and a
+ * wave takes work from its own XCD's list before the others', so the state
+ * lines a chunk touches stay in one L2.  Per-trajectory
  * results do not depend on blocks, refill_min, check_every, lpt, graph or
  * lanes.  With opts->graph the small set-up and analysis launches around
  * the persistent kernel are captured into two HIP graphs on first use (per
