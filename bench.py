@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--learned", action="store_true",
                     help="also train the proposal network and report variance x GPU-seconds, "
                          "learned vs plain, for dissociation of H2(v=4,j=0)+Ca at 5e4 K")
-    ap.add_argument("--learned-replicates", type=int, default=48)
+    ap.add_argument("--learned-replicates", type=int, default=96)
     ap.add_argument("--learned-n", type=int, default=200_000)
     ap.add_argument("--learned-epochs", type=int, default=20)
     return ap.parse_args()
