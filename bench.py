@@ -243,6 +243,9 @@ def main():
         "wall_s": wall,
     }
     res["roofline"]["traffic"] = TRAFFIC.get((args.workload, res["roofline"]["kernel"]))
+    if res["roofline"]["traffic"]:
+        # HBM bandwidth the propagation kernel draws, beside its FP64 rate
+        res["roofline"]["hbm_GB_per_s"] = res["roofline"]["traffic"] / (prop_ms * 1e-3) / 1e9
     if grid_out:
         g = grid_out[-1].cpu().numpy()
         res["grid"] = {"E_c_K": g[:, Q.G_EC].tolist(),

@@ -1541,7 +1541,7 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
     if (!c->d_counter) {
         if (hipMalloc(&c->d_counter, kCounters * sizeof(unsigned long long)) != hipSuccess) {
             c->d_counter = nullptr;
-            return fail(c, QCAMS_ENOMEM, "work counter allocation failed");
+            return fail(c, QCAMS_ENOMEM, "work list counters allocation failed");
         }
     }
     if (c->n_cu == 0) {
