@@ -332,13 +332,14 @@ __global__ void __launch_bounds__(256) k_record(Sys S, Prm P, double* d, int32_t
 // persistent propagation with lane refill
 //
 // Work items w = 0..N-1 are trajectories in longest-expected-first instance
-// order.  Each lane holds one trajectory; when at least `refill_min` lanes of
-// a wave are idle, lane 0 claims that many items with one atomic add and the
-// idle lanes take consecutive items by their rank among the idle lanes
-// (ballot + mbcnt).  A lane picks up its trajectory's initial state (drawn
-// beforehand by the initial-condition kernel) and writes the final state back
-// to the same natural position (instances in id order), where classification
-// and reduction read them.
+// order.  Each slot (a lane, quad or octet) holds one trajectory; when at
+// least `refill_min` slots of a wave are idle, lane 0 claims that many items
+// of a work list with one atomic add and the idle slots take consecutive
+// items of the list by their rank among the idle slots (ballot + mbcnt).  A
+// slot picks up its trajectory's initial state (drawn beforehand by the
+// initial-condition kernel) and writes the final state back to the same
+// natural position (instances in id order), where classification and
+// reduction read them.
 // ---------------------------------------------------------------------------
 // Work of the persistent run, XCD by XCD.  Each XCD (its own L2) has a list
 // of its own: the work order cut into chunks of kChunk consecutive items,
