@@ -44,6 +44,11 @@ struct qcams_ctx {
     unsigned long long* d_counter = nullptr;   // [kCounters] of the persistent run: work cursors, wave steps
     int64_t* d_order = nullptr;                // [n_total] work item -> natural position
     int64_t order_cap = 0;
+    // per-instance reduction in chunks of positions: chunk offsets per
+    // instance and one partial-sum row per chunk
+    int64_t* d_xoff = nullptr;    // [n_inst + 1]
+    double* d_xpart = nullptr;    // [n_xchunks][kPartStride]
+    int64_t n_xchunks = 0, xoff_cap = 0, xpart_cap = 0;
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
     qcams_run_opts last_opts{};                   // effective options of the last run
     bool lj126 = false;                           // pair AB is LJ 12-6
@@ -600,7 +605,7 @@ __global__ void k_classify(Sys S, Prm P, const double* d, const uint8_t* status,
 }
 
 // ---------------------------------------------------------------------------
-// per-instance reduction: one 256-thread block per instance, fixed order
+// per-instance reduction: 256-thread blocks over chunks of positions, fixed order
 // ---------------------------------------------------------------------------
 constexpr int kRedThreads = 256;
 
@@ -630,17 +635,40 @@ __device__ inline void block_sum(double (&v)[NV], double* red)
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(kRedThreads)
-k_xsec(const Inst* inst, int n_inst, double mu123, const uint8_t* label, const int16_t* vt,
-       const double* od, int64_t old, const int64_t* ids, const double* weight, int64_t n,
-       double* xs, double* hist)
+// The reduction of an instance runs in chunks of kXChunk positions, one
+// block per chunk, each writing a row of partial sums; a second kernel adds
+// an instance's rows in chunk order.  Both orders are fixed, so the results
+// do not depend on timing, and an instance that fits in one chunk gets the
+// sums a single block would form.
+constexpr int64_t kXChunk = 4096;
+constexpr int kPartHist = 3 * QCAMS_VMAX;     // (channel q, r1, r2) x v_t
+constexpr int kPartStride = 16 + kPartHist;   // 16 sums, then the histogram
+
+__device__ inline int instance_of_chunk(const int64_t* xoff, int n_inst, int64_t blk)
 {
-    const int k = blockIdx.x;
-    if (k >= n_inst) return;
+    int lo = 0, hi = n_inst - 1, k = 0;
+    while (lo <= hi) {   // last instance whose first chunk is <= blk
+        const int mid = (lo + hi) >> 1;
+        if (xoff[mid] <= blk) { k = mid; lo = mid + 1; }
+        else hi = mid - 1;
+    }
+    return k;
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_xsec_part(const Inst* inst, int n_inst, const int64_t* xoff, const uint8_t* label,
+            const int16_t* vt, const double* od, int64_t old, const int64_t* ids,
+            const double* weight, int64_t n, double* part)
+{
+    const int64_t blk = blockIdx.x;
+    const int k = instance_of_chunk(xoff, n_inst, blk);
     __shared__ double red[16 * kRedThreads];
     const Inst I = inst[k];
-    const int64_t b = lower_bound_ids(ids, n, I.first_id);
-    const int64_t e = lower_bound_ids(ids, n, I.first_id + I.n_traj);
+    const int64_t ib = lower_bound_ids(ids, n, I.first_id);
+    const int64_t ie = lower_bound_ids(ids, n, I.first_id + I.n_traj);
+    const int64_t b = ib + (blk - xoff[k]) * kXChunk;
+    const int64_t e = b + kXChunk < ie ? b + kXChunk : ie;
+    double* row = part + blk * kPartStride;
     // 0..5 counts, 6..9 sum w 1[x], 10..13 sum (w 1[x])^2, 14 sum w, 15 sum w^2
     double acc[16];
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
@@ -658,9 +686,9 @@ k_xsec(const Inst* inst, int n_inst, double mu123, const uint8_t* label, const i
         if (c < 3) vtmax = fmax(vtmax, (double)vt[i]);
     }
     block_sum<16>(acc, red);
-    double m1[1] = {vtmax};
+    if (threadIdx.x < 16) row[threadIdx.x] = acc[threadIdx.x];
     // max-reduce through the same buffer
-    red[threadIdx.x] = m1[0];
+    red[threadIdx.x] = vtmax;
     __syncthreads();
     for (int s = kRedThreads / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
@@ -669,7 +697,6 @@ k_xsec(const Inst* inst, int n_inst, double mu123, const uint8_t* label, const i
     const int vmax_here = (int)fmin(red[0], (double)(QCAMS_VMAX - 1));
     __syncthreads();
     // Gaussian-binning histogram, one fixed-order reduction per (channel, vt)
-    double Wsum = 0.0;
     for (int c = 0; c < 3; ++c) {
         for (int v = 0; v <= vmax_here; ++v) {
             double h[1] = {0.0};
@@ -680,14 +707,37 @@ k_xsec(const Inst* inst, int n_inst, double mu123, const uint8_t* label, const i
                 }
             }
             block_sum<1>(h, red);
-            Wsum += h[0];
-            if (hist && threadIdx.x == 0) hist[((int64_t)k * 3 + c) * QCAMS_VMAX + v] = h[0];
+            if (threadIdx.x == 0) row[16 + c * QCAMS_VMAX + v] = h[0];
         }
-        if (hist && threadIdx.x == 0)
-            for (int v = vmax_here + 1; v < QCAMS_VMAX; ++v)
-                hist[((int64_t)k * 3 + c) * QCAMS_VMAX + v] = 0.0;
+        for (int v = vmax_here + 1 + (int)threadIdx.x; v < QCAMS_VMAX; v += kRedThreads)
+            row[16 + c * QCAMS_VMAX + v] = 0.0;
     }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_xsec(const Inst* inst, int n_inst, const int64_t* xoff, const double* part, double mu123,
+       const int64_t* ids, int64_t n, double* xs, double* hist)
+{
+    const int k = blockIdx.x;
+    if (k >= n_inst) return;
+    __shared__ double tot[kPartStride];
+    // each sum over the instance's chunks in chunk order
+    for (int q = threadIdx.x; q < kPartStride; q += kRedThreads) {
+        double t = 0.0;
+        for (int64_t r = xoff[k]; r < xoff[k + 1]; ++r) t += part[r * kPartStride + q];
+        tot[q] = t;
+    }
+    __syncthreads();
+    if (hist)
+        for (int q = threadIdx.x; q < kPartHist; q += kRedThreads)
+            hist[(int64_t)k * kPartHist + q] = tot[16 + q];
     if (threadIdx.x != 0) return;
+    const Inst I = inst[k];
+    const int64_t b = lower_bound_ids(ids, n, I.first_id);
+    const int64_t e = lower_bound_ids(ids, n, I.first_id + I.n_traj);
+    const double* acc = tot;
+    double Wsum = 0.0;
+    for (int q = 0; q < kPartHist; ++q) Wsum += tot[16 + q];
     double* row = xs + (int64_t)k * QCAMS_XS_STRIDE;
     const double N = (double)(e - b);
     row[0] = N;
@@ -696,7 +746,10 @@ k_xsec(const Inst* inst, int n_inst, double mu123, const uint8_t* label, const i
     const double speed = sqrt(2.0 * I.Ec / mu123);
     for (int c = 0; c < 4; ++c) {
         const double m = N > 0 ? acc[6 + c] / N : NAN;
-        const double var = N > 0 ? acc[10 + c] / N - m * m : NAN;
+        // m^2 rounded on its own (not fused into the difference): a single
+        // trajectory, or all-equal weights, then give a variance of exactly 0
+        const double m2 = m * m;
+        const double var = N > 0 ? acc[10 + c] / N - m2 : NAN;
         const double se = sqrt(fmax(var, 0.0) / N);
         row[7 + c] = m;
         row[11 + c] = se;
@@ -1079,7 +1132,7 @@ void qcams_destroy(qcams_ctx* c)
     for (int e = 0; e < 2; ++e)
         if (c->ev_prop[e]) (void)hipEventDestroy(c->ev_prop[e]);
     for (void* q : {(void*)c->d_prop_q, (void*)c->d_prop_cdf, (void*)c->d_cell_x, (void*)c->d_cell_p,
-                    (void*)c->d_grid_inst, (void*)c->d_grid_off})
+                    (void*)c->d_grid_inst, (void*)c->d_grid_off, (void*)c->d_xoff, (void*)c->d_xpart})
         if (q) (void)hipFree(q);
     delete c;
 }
@@ -1317,6 +1370,32 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
     // rank correlations 0.994 and 0.986 (1/(v_c tau): 0.995, 0.969)
     std::vector<int64_t> nat(n_inst + 1, 0), loff(n_inst + 1, 0);
     for (int k = 0; k < n_inst; ++k) nat[k + 1] = nat[k] + h[k].n_traj;
+    // reduction chunks: at least one per instance
+    {
+        std::vector<int64_t> xoff(n_inst + 1, 0);
+        for (int k = 0; k < n_inst; ++k) {
+            const int64_t m = (h[k].n_traj + kXChunk - 1) / kXChunk;
+            xoff[k + 1] = xoff[k] + (m > 0 ? m : 1);
+        }
+        const int64_t nch = xoff[n_inst];
+        if (nch > 0x7fffffff) return fail(c, QCAMS_EINVAL, "too many reduction chunks");
+        if (n_inst + 1 > c->xoff_cap || nch > c->xpart_cap) {
+            if (c->d_xoff) (void)hipFree(c->d_xoff);
+            if (c->d_xpart) (void)hipFree(c->d_xpart);
+            c->d_xoff = nullptr;
+            c->d_xpart = nullptr;
+            c->xoff_cap = c->xpart_cap = 0;
+            c->graph_key[0] = 0;
+            if (hipMalloc(&c->d_xoff, (n_inst + 1) * sizeof(int64_t)) != hipSuccess ||
+                hipMalloc(&c->d_xpart, nch * kPartStride * sizeof(double)) != hipSuccess)
+                return fail(c, QCAMS_ENOMEM, "reduction table allocation failed");
+            c->xoff_cap = n_inst + 1;
+            c->xpart_cap = nch;
+        }
+        HIP_OK(c, hipMemcpy(c->d_xoff, xoff.data(), (n_inst + 1) * sizeof(int64_t),
+                            hipMemcpyHostToDevice));
+        c->n_xchunks = nch;
+    }
     std::vector<int32_t> order(n_inst);
     std::vector<double> cost(n_inst);
     for (int k = 0; k < n_inst; ++k) {
@@ -1407,6 +1486,17 @@ int qcams_classify(qcams_ctx* c, const qcams_state* st, int64_t n, const qcams_o
     return QCAMS_OK;
 }
 
+// the two reduction kernels: partial sums per chunk, then per instance
+static void launch_xsec(qcams_ctx* c, const qcams_outcome* out, const int64_t* ids,
+                        const double* weight, int64_t n, double* xs, double* hist, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_xsec_part, dim3((unsigned)c->n_xchunks), dim3(kRedThreads), 0, s, c->d_inst,
+                       c->n_inst, c->d_xoff, out->label, out->vt, out->d, out->ld, ids, weight, n,
+                       c->d_xpart);
+    hipLaunchKernelGGL(k_xsec, dim3(c->n_inst), dim3(kRedThreads), 0, s, c->d_inst, c->n_inst,
+                       c->d_xoff, c->d_xpart, c->sys.mu123, ids, n, xs, hist);
+}
+
 int qcams_cross_sections(qcams_ctx* c, const qcams_outcome* out, const int64_t* ids,
                          const double* weight, int64_t n, double* xs, double* hist, void* stream)
 {
@@ -1415,9 +1505,7 @@ int qcams_cross_sections(qcams_ctx* c, const qcams_outcome* out, const int64_t* 
     if (!out || !xs || n < 0 || (n > 0 && (!ids || !out->label || !out->vt || !out->d || out->ld < n)))
         return fail(c, QCAMS_EINVAL, "bad arguments");
     HIP_OK(c, hipSetDevice(c->device));
-    hipLaunchKernelGGL(k_xsec, dim3(c->n_inst), dim3(kRedThreads), 0, (hipStream_t)stream,
-                       c->d_inst, c->n_inst, c->sys.mu123, out->label, out->vt, out->d, out->ld,
-                       ids, weight, n, xs, hist);
+    launch_xsec(c, out, ids, weight, n, xs, hist, (hipStream_t)stream);
     HIP_OK(c, hipGetLastError());
     return QCAMS_OK;
 }
@@ -1495,10 +1583,8 @@ static void enqueue_post(qcams_ctx* c, const qcams_state* st, const qcams_outcom
     const int64_t n = c->n_total;
     hipLaunchKernelGGL(k_classify, dim3(grid_of(n, 128)), dim3(128), 0, s, c->sys, c->prm, st->d,
                        st->status, st->ld, n, out->label, out->vt, out->jt, out->d, out->ld);
-    hipLaunchKernelGGL(k_xsec, dim3(c->n_inst), dim3(kRedThreads), 0, s, c->d_inst, c->n_inst,
-                       c->sys.mu123, out->label, out->vt, out->d, out->ld, (const int64_t*)ids,
-                       sample ? (const double*)(sample + 5 * st->ld) : (const double*)nullptr, n,
-                       xs, hist);
+    launch_xsec(c, out, ids, sample ? (const double*)(sample + 5 * st->ld) : (const double*)nullptr,
+                n, xs, hist, s);
 }
 
 static int capture(qcams_ctx* c, hipGraph_t* g, hipGraphExec_t* x, const std::function<void(hipStream_t)>& f)
@@ -1579,7 +1665,7 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
                               (uint64_t)st->status, (uint64_t)st->ld, (uint64_t)sample,
                               (uint64_t)out->label, (uint64_t)out->d, (uint64_t)out->ld,
                               (uint64_t)ids, (uint64_t)xs, (uint64_t)hist,
-                              (uint64_t)o.lpt | ((uint64_t)o.rk << 8),
+                              (uint64_t)o.lpt | ((uint64_t)o.rk << 8) | ((uint64_t)c->n_xchunks << 16),
                               (uint64_t)out->vt ^ ((uint64_t)out->jt << 1),
                               (uint64_t)c->n_total ^ ((uint64_t)c->n_inst << 40)};
     if (memcmp(key, c->graph_key, sizeof key) != 0) {

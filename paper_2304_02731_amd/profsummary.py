@@ -9,6 +9,12 @@ import argparse
 import sqlite3
 
 
+def short_name(name: str) -> str:
+    """Kernel name without its argument list (and without the anonymous
+    namespace's prefix, whose parenthesis would cut it short)."""
+    return name.replace("(anonymous namespace)::", "").split("(")[0]
+
+
 def kernel_stats(db: str):
     """(name, calls, total ns, average ns, percent) from the dispatch table."""
     c = sqlite3.connect(db)
@@ -36,7 +42,7 @@ def main():
         print("| kernel | calls | total ms | average ms | % |")
         print("|---|---|---|---|---|")
         for name, n, tot, avg, pct in ks:
-            print("| %s | %d | %.3f | %.3f | %.2f |" % (name.split("(")[0], n, tot / 1e6, avg / 1e6, pct))
+            print("| %s | %d | %.3f | %.3f | %.2f |" % (short_name(name), n, tot / 1e6, avg / 1e6, pct))
     cs = counters(a.db)
     if cs:
         print()
@@ -44,7 +50,7 @@ def main():
         print("|---|---|---|---|")
         f64 = {}
         for kname, cname, v, nd in cs:
-            short = kname.split("(")[0]
+            short = short_name(kname)
             print("| %s | %s | %.6g | %d |" % (short, cname, v, nd))
             if "propagate" in short:
                 f64[cname] = v

@@ -302,6 +302,55 @@ def test_classify_same_final_state(Q, torch, orc):
     assert np.allclose(xs[sel, Q.XS_WTOT], Wt[sel], rtol=1e-6, atol=1e-9)
 
 
+def test_reduction_over_large_instances(Q, torch, orc):
+    """The per-instance reduction runs in chunks of 4096 positions: on
+    synthetic outcomes (labels of every kind, v_t bins, Gaussian weights and
+    importance weights) over instances of 1, 4,096, 4,097 and 70,000
+    trajectories, with ids missing here and there, counts equal the oracle's
+    exactly and probabilities, errors, histograms and total weights agree to
+    rounding."""
+    s = W.h2ca_system()
+    sizes = [1, 4096, 4097, 70000]
+    inst, first = [], 0
+    for k, m in enumerate(sizes):
+        inst.append(W.Instance(1e4 * (k + 1), 0, 0, m, first, 99, W.B_AREA, 0.0, 8.0))
+        first += m + 7
+    wl = W.Workload("reduction", s, W.Params(), inst)
+    rng = np.random.default_rng(17)
+    ids = np.concatenate([np.arange(I.first_id, I.first_id + I.n_traj) for I in inst])
+    ids = np.sort(ids[rng.random(len(ids)) > 0.03] if len(ids) > 1 else ids)
+    ids = np.unique(np.r_[ids, inst[0].first_id])
+    n = len(ids)
+    lab = rng.choice(6, n, p=[0.55, 0.1, 0.1, 0.15, 0.05, 0.05]).astype(np.uint8)
+    vt = rng.integers(0, 21, n).astype(np.int16)
+    wgb = rng.random(n)
+    w = 0.2 + 1.6 * rng.random(n)
+    ctx = _ctx(Q, wl)
+    out = ctx.new_outcome(n)
+    out.label.copy_(torch.as_tensor(lab))
+    out.vt.copy_(torch.as_tensor(vt))
+    od = np.zeros((4, n))
+    od[2] = wgb
+    out.d.copy_(torch.as_tensor(od))
+    tid = torch.as_tensor(ids, device="cuda:0")
+    xs, hist = ctx.cross_sections(out, tid, weight=torch.as_tensor(w, device="cuda:0"))
+    torch.cuda.synchronize()
+    xs, hist = xs.cpu().numpy(), hist.cpu().numpy()
+    which = _inst_of(wl, ids)
+    ref = orc.cross_sections(wl, lab, w, which)
+    assert np.array_equal(xs[:, 0], np.bincount(which, minlength=len(inst)))
+    assert np.array_equal(xs[:, 1:7], ref["counts"].astype(float))
+    assert np.allclose(xs[:, 7:11], ref["P"], rtol=1e-13, atol=1e-16)
+    assert np.allclose(xs[:, 11:15], ref["dP"], rtol=1e-10, atol=1e-15)
+    assert np.allclose(xs[:, 15:19], ref["sigma"], rtol=1e-13, atol=1e-16)
+    # the histogram carries importance weight x Gaussian weight
+    H, Wt = orc.gb_distributions(wl, lab, vt, w * wgb, which, vmax=Q.VMAX)
+    assert np.allclose(hist, H, rtol=1e-12, atol=1e-12)
+    # W of Eq. (15) on the GPU counts dissociation with its importance weight
+    wd = np.bincount(which, weights=w * (lab == Q.DISS), minlength=len(inst))
+    assert np.allclose(xs[:, Q.XS_WTOT], H.sum(axis=(1, 2)) + wd, rtol=1e-12)
+
+
 @RK_VARIANTS
 def test_cross_sections_statistical(Q, torch, orc, rk):
     """Independent full runs (GPU vs oracle, same seeds): per-channel cross
