@@ -1278,17 +1278,35 @@ int qcams_set_instances(qcams_ctx* c, const qcams_instance* inst, int32_t n_inst
         vv[k] = q.v;
         jj[k] = q.j;
     }
-    std::vector<double> lev(4 * (size_t)n_inst);
+    // levels of the distinct (v, j) pairs only (instances share them: a grid
+    // of energies repeats every state)
+    std::vector<int32_t> uv, uj, which(n_inst);
+    {
+        std::map<std::pair<int32_t, int32_t>, int32_t> seen;
+        for (int k = 0; k < n_inst; ++k) {
+            const auto key = std::make_pair(vv[k], jj[k]);
+            auto it = seen.find(key);
+            if (it == seen.end()) {
+                it = seen.emplace(key, (int32_t)uv.size()).first;
+                uv.push_back(vv[k]);
+                uj.push_back(jj[k]);
+            }
+            which[k] = it->second;
+        }
+    }
+    const int n_lev = (int)uv.size();
+    std::vector<double> lev(4 * (size_t)n_lev);
     int rc = c->level_method == QCAMS_LEVELS_DVR
-                 ? qcams_dvr_levels(c, c->dvr_npts, c->dvr_xmin, c->dvr_xmax, n_inst, vv.data(),
-                                    jj.data(), lev.data())
-                 : qcams_levels(c, n_inst, vv.data(), jj.data(), lev.data());
+                 ? qcams_dvr_levels(c, c->dvr_npts, c->dvr_xmin, c->dvr_xmax, n_lev, uv.data(),
+                                    uj.data(), lev.data())
+                 : qcams_levels(c, n_lev, uv.data(), uj.data(), lev.data());
     if (rc != QCAMS_OK) return rc;
     for (int k = 0; k < n_inst; ++k) {
-        h[k].Evj = lev[4 * k + 0];
-        h[k].rminus = lev[4 * k + 1];
-        h[k].rplus = lev[4 * k + 2];
-        h[k].tau = lev[4 * k + 3];
+        const double* L = &lev[4 * (size_t)which[k]];
+        h[k].Evj = L[0];
+        h[k].rminus = L[1];
+        h[k].rplus = L[2];
+        h[k].tau = L[3];
         const double b = inst[k].b_mode == QCAMS_B_FIXED ? inst[k].b : inst[k].bmax;
         if (!(b < c->prm.R0)) return fail(c, QCAMS_EINVAL, "instance %d: impact parameter >= R0", k);
     }
