@@ -35,7 +35,7 @@ F_STEP = {("morse", 0): 1833.7, ("morse", 1): 3996.7,
 # HBM bytes per launch of the persistent kernel from FETCH_SIZE and WRITE_SIZE
 # passes scaled by a streaming kernel of known size, for the kernel as it was
 # when the counters were taken (workload, kernel) -> bytes; null otherwise.
-TRAFFIC = {("batched", "k_persistent<4,0,0,0,1>"): 32.38e6}
+TRAFFIC = {("batched", "k_persistent<4,0,0,0,1>"): 32.70e6}
 RK_NAMES = {"dopri5": 0, "dop853": 1}
 KINDS = {"morse": "0,0,0", "mixed": "3,0,2"}   # 3: LJ 12-6 specialisation
 # workload -> (surface, default CPU-baseline stride)
