@@ -26,6 +26,12 @@
  *    context.
  *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
  *    marked "async" only enqueue kernels on it; calls marked "sync" block.
+ *    A context's device work tables (the persistent run's work lists and
+ *    wave-step count, the reduction's per-chunk partial sums) are shared by
+ *    its calls: qcams_run and qcams_cross_sections calls on one context must
+ *    not overlap on different streams (one stream per context, or a context
+ *    per stream); qcams_set_instances must not overlap queued work of the
+ *    context either.
  *  - Determinism: every result is a pure function of (system, params,
  *    instances, seed, trajectory id); integer results are bit-reproducible
  *    and floating-point reductions use a fixed order.
