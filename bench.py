@@ -94,8 +94,22 @@ def cpu_baseline(wl, stride, procs):
     nth = {1: "", 2: "2nd ", 3: "3rd "}.get(stride, "%dth " % stride)
     return {"value": n / dt, "unit": "trajectories/s", "cores": procs, "kind": "oracle",
             "sample": "every %strajectory id of all %d instances (%d trajectories), "
-                      "serial C oracle in a %d-process pool, %.1f s"
-                      % (nth, len(wl.instances), n, procs, dt)}
+                      "serial C oracle in a %d-process pool, %.1f s, on %s"
+                      % (nth, len(wl.instances), n, procs, dt, host_cpu())}
+
+
+def host_cpu() -> str:
+    """Model and logical CPU count of the host."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%s (%d logical CPUs)" % (model, os.cpu_count() or 0)
 
 
 def main():
