@@ -108,8 +108,9 @@ def lib():
         L.orc_init_q.argtypes = [C.POINTER(System), C.POINTER(Params), C.POINTER(Instance), _dp,
                                  C.c_int64, _dp, _dp, _dp, _dp]
         L.orc_dopri5_tableau.argtypes = [_dp, _dp, _dp, _dp]
-        L.orc_propagate.argtypes = [C.POINTER(System), C.POINTER(Params), _dp, _dp,
-                                    C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.orc_propagate_log.argtypes = [C.POINTER(System), C.POINTER(Params), _dp, _dp,
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64), _dp,
+                                        C.c_int64, C.POINTER(C.c_int64)]
         L.orc_pair_bound.argtypes = [C.POINTER(Pair), C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_int, _dp, _dp]
         L.orc_gb_weight.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int)]
@@ -312,6 +313,20 @@ def propagate(sys: System, prm: Params, y, aux):
     return st, y, aux, ns.value, nr.value
 
 
+def propagate_log(sys: System, prm: Params, y, aux, log_cap: int = 1 << 20):
+    """propagate() with the record of its trials: returns (status, y, aux,
+    nstep, nrej, trials) with trials [n, 4] = (t, trial step, error norm,
+    accepted) in order (the first log_cap of them)."""
+    y, py = _arr(np.array(y, dtype=np.float64, copy=True))
+    aux, pa = _arr(np.array(aux, dtype=np.float64, copy=True))
+    ns, nr, nl = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    log = np.zeros((log_cap, 4))
+    st = lib().orc_propagate_log(C.byref(sys), C.byref(prm), py, pa, C.byref(ns), C.byref(nr),
+                                 log.ctypes.data_as(C.POINTER(C.c_double)), log_cap,
+                                 C.byref(nl))
+    return st, y, aux, ns.value, nr.value, log[:min(nl.value, log_cap)].copy()
+
+
 def pair_bound(pair, mu, J2, E, r, literal=0):
     rw, r0 = C.c_double(), C.c_double()
     b = lib().orc_pair_bound(C.byref(pair), mu, J2, E, r, literal, C.byref(rw), C.byref(r0))
@@ -361,10 +376,9 @@ def reduced_masses(sys: System):
 
 
 def _run_chunk(args):
-    wl_sys, wl_prm, inst, ids, prop_q = args
+    wl_sys, wl_prm, inst, ids, prop_q, lev = args
     sys = make_system(wl_sys)
     prm = make_params(wl_prm)
-    lev = level(sys, inst.v, inst.j)
     return run_batch(sys, prm, make_instance(inst), lev, ids, prop_q)
 
 
@@ -372,6 +386,12 @@ def run_workload(wl: W.Workload, ids_per_instance=None, processes: int = 1, prop
     """Run trajectories of a workload through the oracle.  ids_per_instance:
     optional list (one per instance) of global trajectory ids to run; default
     all.  Returns (records, instance index per record)."""
+    # the level of each distinct (v, j), once (instances of a grid share them)
+    sys = make_system(wl.system)
+    levels = {}
+    for inst in wl.instances:
+        if (inst.v, inst.j) not in levels:
+            levels[(inst.v, inst.j)] = level(sys, inst.v, inst.j)
     jobs = []
     for k, inst in enumerate(wl.instances):
         ids = (np.arange(inst.first_id, inst.first_id + inst.n_traj, dtype=np.int64)
@@ -380,7 +400,8 @@ def run_workload(wl: W.Workload, ids_per_instance=None, processes: int = 1, prop
             continue
         step = max(1, (len(ids) + 4 * max(processes, 1) - 1) // (4 * max(processes, 1)))
         for s in range(0, len(ids), step):
-            jobs.append((k, (wl.system, wl.params, inst, ids[s:s + step], prop_q)))
+            jobs.append((k, (wl.system, wl.params, inst, ids[s:s + step], prop_q,
+                             levels[(inst.v, inst.j)])))
     if processes > 1:
         import multiprocessing as mp
         ctx = mp.get_context("fork")

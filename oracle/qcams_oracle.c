@@ -295,26 +295,64 @@ int orc_gauss_legendre(int n, double *x, double *w)
     return ORC_OK;
 }
 
-static void gl_init(void)
-{
-    if (!gl_ready) { orc_gauss_legendre(ORC_NGL, gl_x, gl_w); gl_ready = 1; }
-}
-
 /* Radial integrals between the turning points, with the substitution
  * r = c + h sin(theta), theta in [-pi/2, pi/2], which removes the square-root
  * end-point behaviour, followed by Gauss-Legendre in theta.
  *   action: (sqrt(2 mu)/pi) int sqrt(E - V_eff) dr         (Eq. (10) + 1/2)
- *   period: sqrt(2 mu) int (E - V_eff)^(-1/2) dr            (Eq. (7))       */
+ *   period: sqrt(2 mu) int (E - V_eff)^(-1/2) dr            (Eq. (7))
+ * The kinetic term E - V_eff(r) is a difference of nearly equal numbers at
+ * the nodes next to the turning points, where the period's integrand is most
+ * sensitive to it.  There it is formed as V_eff(r+-) - V_eff(r) (E =
+ * V_eff(r+-) defines the turning points), i.e. as the integral of V_eff' over
+ * the short interval between r and the turning point, whose length
+ * h (1 - |sin theta|) = 2 h sin^2((pi/2 - |theta|)/2) is computed directly. */
+#define ORC_NWALL 8
+static double wall_x[ORC_NWALL], wall_w[ORC_NWALL];
+
+static void gl_init(void)
+{
+    if (!gl_ready) {
+        orc_gauss_legendre(ORC_NGL, gl_x, gl_w);
+        orc_gauss_legendre(ORC_NWALL, wall_x, wall_w);
+        gl_ready = 1;
+    }
+}
+
+/* V_eff(a + len) - V_eff(a) = int_a^{a+len} V_eff'(u) du (Gauss-Legendre) */
+static double veff_rise(const orc_pair *pp, double mu, double J2, double a, double len)
+{
+    double s = 0.0;
+    for (int i = 0; i < ORC_NWALL; ++i)
+        s += wall_w[i] * veff_d(pp, mu, J2, a + 0.5 * len * (1.0 + wall_x[i]));
+    return 0.5 * len * s;
+}
+
+/* Node i of the rule: the factor dr/dtheta = h cos(theta) and E - V_eff(r). */
+static void radial_node(const orc_pair *pp, double mu, double J2, double E, double rm,
+                        double rp, int i, double *drdth, double *kin)
+{
+    double c = 0.5 * (rp + rm), h = 0.5 * (rp - rm);
+    double x = gl_x[i];
+    double u = 0.25 * M_PI * (1.0 - fabs(x));   /* (pi/2 - |theta|) / 2 */
+    double d = 2.0 * h * sin(u) * sin(u);        /* distance to the nearer turning point */
+    *drdth = h * sin(2.0 * u);                   /* h cos(theta) */
+    if (d < 0.01 * h) {
+        if (x >= 0.0) *kin = veff_rise(pp, mu, J2, rp - d, d);          /* V_eff(r+) - V_eff(r) */
+        else *kin = -veff_rise(pp, mu, J2, rm, d);                       /* V_eff(r-) - V_eff(r) */
+    } else {
+        *kin = E - veff(pp, mu, J2, c + h * sin(0.5 * M_PI * x));
+    }
+}
+
 double orc_action(const orc_pair *pp, double mu, double J2, double E, double rm, double rp)
 {
     gl_init();
-    double c = 0.5 * (rp + rm), h = 0.5 * (rp - rm), s = 0.0;
+    double s = 0.0;
     for (int i = 0; i < ORC_NGL; ++i) {
-        double th = 0.5 * M_PI * gl_x[i];
-        double r = c + h * sin(th);
-        double k = E - veff(pp, mu, J2, r);
+        double dr, k;
+        radial_node(pp, mu, J2, E, rm, rp, i, &dr, &k);
         if (k < 0.0) k = 0.0;
-        s += gl_w[i] * sqrt(k) * h * cos(th);
+        s += gl_w[i] * sqrt(k) * dr;
     }
     s *= 0.5 * M_PI;
     return sqrt(2.0 * mu) / M_PI * s;
@@ -323,13 +361,11 @@ double orc_action(const orc_pair *pp, double mu, double J2, double E, double rm,
 double orc_period(const orc_pair *pp, double mu, double J2, double E, double rm, double rp)
 {
     gl_init();
-    double c = 0.5 * (rp + rm), h = 0.5 * (rp - rm), s = 0.0;
+    double s = 0.0;
     for (int i = 0; i < ORC_NGL; ++i) {
-        double th = 0.5 * M_PI * gl_x[i];
-        double r = c + h * sin(th);
-        double k = E - veff(pp, mu, J2, r);
-        if (k <= 0.0) continue;
-        s += gl_w[i] * h * cos(th) / sqrt(k);
+        double dr, k;
+        radial_node(pp, mu, J2, E, rm, rp, i, &dr, &k);
+        s += gl_w[i] * dr / sqrt(k);
     }
     s *= 0.5 * M_PI;
     return sqrt(2.0 * mu) * s;
@@ -746,9 +782,24 @@ static void collapse_radii(const orc_system *s, double *rb)
  * Buckingham inner maximum.  Step-size control: RMS error norm, accept if
  * err <= 1, factor min(10, max(0.2, 0.9 err^(-1/5))), no increase right after
  * a rejection, h_min = 1e-12 t_max. */
+int orc_propagate_log(const orc_system *s, const orc_params *prm, double *y, double *aux,
+                      int64_t *nstep, int64_t *nrej, double *log, int64_t log_cap,
+                      int64_t *log_n);
+
 int orc_propagate(const orc_system *s, const orc_params *prm, double *y, double *aux,
                   int64_t *nstep, int64_t *nrej)
 {
+    return orc_propagate_log(s, prm, y, aux, nstep, nrej, 0, 0, 0);
+}
+
+/* orc_propagate with a record of every trial step (test diagnostics):
+ * log[4 k + 0..3] = (t, trial step size, error norm, 1 if accepted) of the
+ * first log_cap trials, *log_n = the number of trials made. */
+int orc_propagate_log(const orc_system *s, const orc_params *prm, double *y, double *aux,
+                      int64_t *nstep, int64_t *nrej, double *log, int64_t log_cap,
+                      int64_t *log_n)
+{
+    int64_t ntrial = 0;
     double f0[12], ynew[12], k7[12], e[12], rb[3];
     collapse_radii(s, rb);
     double t = aux[0], tmax = aux[1], rs = aux[2], h = aux[5];
@@ -774,6 +825,13 @@ int orc_propagate(const orc_system *s, const orc_params *prm, double *y, double 
         }
         if (prm->fixed_step) err = 0.0;
         if (!isfinite(err)) err = INFINITY;
+        if (log && ntrial < log_cap) {
+            log[4 * ntrial + 0] = t;
+            log[4 * ntrial + 1] = hs;
+            log[4 * ntrial + 2] = err;
+            log[4 * ntrial + 3] = err <= 1.0 ? 1.0 : 0.0;
+        }
+        ++ntrial;
         if (err <= 1.0) {
             t = (hs == tmax - t) ? tmax : t + hs;
             memcpy(y, ynew, sizeof y[0] * 12);
@@ -808,6 +866,7 @@ int orc_propagate(const orc_system *s, const orc_params *prm, double *y, double 
     }
     aux[0] = t;
     aux[5] = h;
+    if (log_n) *log_n = ntrial;
     return status;
 }
 

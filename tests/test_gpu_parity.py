@@ -49,12 +49,14 @@ def test_levels_match_oracle(Q, orc):
         sys = orc.make_system(wl.system)
         vs, js = zip(*[(v, j) for v in range(0, 6) for j in range(0, 11, 2)])
         g = ctx.levels(vs, js)
-        for k, (v, j) in enumerate(zip(vs, js)):
-            o = orc.level(sys, v, j)
-            assert g[k, 0] == pytest.approx(o[0], rel=1e-12), (v, j)
-            assert g[k, 1] == pytest.approx(o[1], rel=1e-11), (v, j)
-            assert g[k, 2] == pytest.approx(o[2], rel=1e-11), (v, j)
-            assert g[k, 3] == pytest.approx(o[3], rel=1e-8), (v, j)
+        o = np.array([orc.level(sys, v, j) for v, j in zip(vs, js)])
+        rel = np.abs(g / o - 1.0).max(axis=0)
+        print(wl.name, "largest relative difference of E, r-, r+, tau:", rel)
+        # both quadratures converge to rounding: the oracle's 256-node
+        # Gauss-Legendre rule and the GPU's 48-node midpoint rule each keep
+        # Eq. (7) within 1e-13 of the Morse closed form below the top levels
+        assert rel[0] < 1e-13 and rel[1] < 1e-12 and rel[2] < 1e-12, rel
+        assert rel[3] < 2e-12, rel
         ctx.close()
 
 
@@ -108,14 +110,12 @@ def test_init_matches_oracle(Q, torch, orc):
         y, aux, sm = orc.init(sys, prm, orc.make_instance(I), levs[k], int(i))
         assert np.array_equal(s[:5, c], sm[:5]), i            # same draws, bit-exact
         assert s[5, c] == 1.0
-        # R of Eq. (6) carries tau, which the oracle's quadrature gives to
-        # ~1e-10 relative: allow that on the R-dependent quantities
-        dR = 1e-10 * (aux[2] - wl.params.r_stop) + 1e-14 * aux[2]
+        # every field to 1e-13 relative, including the R-dependent ones
+        # (rho2_z, t_max, r_stop_eff) that carry tau of Eq. (7) through Eq. (6)
         rel = np.abs(d[:12, c] - y) / np.maximum(np.abs(y), 1.0)
-        assert rel[[0, 1, 2, 3, 4, 6, 7, 8, 9, 10, 11]].max() < 1e-13, (i, rel.max())
-        assert abs(d[5, c] - y[5]) <= dR + 1e-14 * abs(y[5]), i
-        assert abs(d[Q.F_TMAX, c] - aux[1]) <= aux[1] * (dR / wl.params.R0 + 1e-13), i
-        assert abs(d[Q.F_RSTOP, c] - aux[2]) <= dR, i
+        assert rel.max() < 1e-13, (i, rel.max())
+        assert d[Q.F_TMAX, c] == pytest.approx(aux[1], rel=1e-13), i
+        assert d[Q.F_RSTOP, c] == pytest.approx(aux[2], rel=1e-13), i
         assert d[Q.F_E0, c] == pytest.approx(aux[3], rel=1e-11, abs=1e-14)
         assert d[Q.F_ESCALE, c] == pytest.approx(aux[4], rel=1e-11)
 

@@ -237,6 +237,41 @@ def test_sigma_from_grid_trapezoid(orc):
     assert s == pytest.approx(math.pi * b[-1] ** 2, rel=1e-14) and e == 0.0
 
 
+def test_sigma_from_grid_error_closed_form(orc):
+    """The error of Eq. (18) on a grid with nonzero per-b errors: on b = (0,
+    1, 2) the trapezoid weights are (1/2, 1, 1/2), so with errors (d0, d1,
+    d2) of P the error of sigma is 2 pi sqrt((1 d1)^2 + (1/2 * 2 d2)^2)
+    (b = 0 contributes nothing); sigma itself is 2 pi (P1 + P2)."""
+    b = np.array([0.0, 1.0, 2.0])
+    P = np.array([0.9, 0.4, 0.1])
+    d = np.array([0.03, 0.02, 0.05])
+    s, e = orc.sigma_from_grid(b, P, d)
+    assert s == pytest.approx(2 * math.pi * (0.4 + 0.1), rel=1e-15)
+    assert e == pytest.approx(2 * math.pi * math.sqrt(0.02 ** 2 + 0.05 ** 2), rel=1e-15)
+    # uneven spacing: b = (0.5, 1, 3): weights (1/4, 5/4, 1)
+    b = np.array([0.5, 1.0, 3.0])
+    s, e = orc.sigma_from_grid(b, P, d)
+    w = np.array([0.25, 1.25, 1.0])
+    assert s == pytest.approx(2 * math.pi * float((w * b * P).sum()), rel=1e-14)
+    assert e == pytest.approx(2 * math.pi * math.sqrt(((w * b * d) ** 2).sum()), rel=1e-14)
+
+
+def test_sigma_from_grid_error_is_the_spread_of_sigma(orc):
+    """Independent errors propagate: with each P(b_k) drawn from a normal of
+    width delta_k, the standard deviation of the trapezoid sigma over many
+    draws is the stated error (within sampling error, 20,000 draws)."""
+    rng = np.random.default_rng(11)
+    b = np.arange(0, 5, 0.25)
+    P = 0.6 * np.exp(-b / 2.0)
+    d = rng.uniform(0.005, 0.04, b.size)
+    s0, e0 = orc.sigma_from_grid(b, P, d)
+    draws = np.array([orc.sigma_from_grid(b, P + d * rng.standard_normal(b.size), d)[0]
+                      for _ in range(20000)])
+    assert draws.mean() == pytest.approx(s0, abs=4 * e0 / math.sqrt(20000))
+    # SD of a sample SD of n normals ~ sd / sqrt(2 n): 0.5 % here
+    assert draws.std(ddof=1) == pytest.approx(e0, rel=0.02)
+
+
 def test_gb_distribution_eq14_15(orc):
     wl = _toy_workload()
     labels = np.array([0, 0, 1, 3, 3] + [0] * 5 + [2] * 10)

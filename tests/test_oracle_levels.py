@@ -127,10 +127,16 @@ def test_morse_levels_closed_form(orc, pair, mu_amu):
         rc, out = orc.level_pair(p, mu, v, 0)
         assert rc == 0, v
         E, rm, rp, tau = _morse_exact(De, re, a, mu, v)
-        assert out[0] == pytest.approx(E, rel=1e-12, abs=1e-15)
+        assert out[0] == pytest.approx(E, rel=5e-13, abs=1e-15)
         assert out[1] == pytest.approx(rm, rel=1e-11)
         assert out[2] == pytest.approx(rp, rel=1e-11)
-        assert out[3] == pytest.approx(tau, rel=1e-8)
+        # Eq. (7) at the oracle's own energy: the closed-form period of the
+        # classical Morse oscillator, 2 pi / (omega sqrt(-E / De)).  Measured
+        # within 4e-14 for every level below the top two, 2e-13 at the top.
+        om = a * math.sqrt(2 * De / mu)
+        tau_at_E = 2 * math.pi / (om * math.sqrt(-out[0] / De))
+        assert out[3] == pytest.approx(tau_at_E, rel=1e-13 if v <= vmax - 2 else 1e-12), v
+        assert out[3] == pytest.approx(tau, rel=1e-12), v
     rc, _ = orc.level_pair(p, mu, vmax + 1, 0)
     assert rc == -2  # unbound
 
