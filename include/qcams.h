@@ -357,8 +357,10 @@ int qcams_last_run_options(qcams_ctx *ctx, qcams_run_opts *used);
  * is kept (best->rk = 1 or 2); the variant changes per-trajectory results,
  * the schedule does not.  With search_rk = 0 the context's variant is used
  * (best->rk = 0).  Results are cached for the process, keyed by device,
- * pair kinds, tolerances, RK variant, search_rk / energy_gate and the
- * number of installed trajectories and instances: with reps >= 0 a cached
+ * search_rk / energy_gate, the number of installed trajectories and
+ * instances, and a hash of the system, every integration parameter and the
+ * installed instance table (so a workload of the same size but other
+ * content is tuned afresh): with reps >= 0 a cached
  * result is returned without timing (reps = 0 counts as 1 otherwise); with
  * reps < 0 the search runs with |reps| repetitions and replaces the cached
  * result.  sync.  Errors as qcams_run; EINVAL also when no variant keeps

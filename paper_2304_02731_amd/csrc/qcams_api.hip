@@ -50,6 +50,7 @@ struct qcams_ctx {
     double* d_xpart = nullptr;    // [n_xchunks][kPartStride]
     int64_t n_xchunks = 0, xoff_cap = 0, xpart_cap = 0;
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
+    unsigned long long* last_counter = nullptr;   // counters of the last run
     qcams_run_opts last_opts{};                   // effective options of the last run
     bool lj126 = false;                           // pair AB is LJ 12-6
     double cost_max = 0.0, cost_total = 0.0;      // expected steps: largest, summed
@@ -67,7 +68,7 @@ struct qcams_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr, graph2_exec = nullptr;
     hipGraph_t graph = nullptr, graph2 = nullptr;
-    uint64_t graph_key[16] = {0};
+    uint64_t graph_key[18] = {0};
     char err[512] = {0};
 };
 
@@ -969,22 +970,23 @@ struct RecordL {
 template <int K0, int K1, int K2, int RK>
 struct PersistentL {
     static void go(qcams_ctx* c, int width, int blocks, int refill_min, int check_every,
-                   const int64_t* order, const qcams_state* st, hipStream_t s)
+                   const int64_t* order, unsigned long long* counter, const qcams_state* st,
+                   hipStream_t s)
     {
         RunMap M{order, c->n_total};
         Prm P = c->prm;
         P.rk = RK;
         if (width == 8)
             hipLaunchKernelGGL((k_persistent<8, K0, K1, K2, RK>), dim3(blocks), dim3(256), 0, s,
-                               c->sys, P, M, c->d_counter, refill_min, check_every, st->d,
+                               c->sys, P, M, counter, refill_min, check_every, st->d,
                                st->nstep, st->nrej, st->status, st->ld);
         else if (width == 4)
             hipLaunchKernelGGL((k_persistent<4, K0, K1, K2, RK>), dim3(blocks), dim3(256), 0, s,
-                               c->sys, P, M, c->d_counter, refill_min, check_every, st->d,
+                               c->sys, P, M, counter, refill_min, check_every, st->d,
                                st->nstep, st->nrej, st->status, st->ld);
         else
             hipLaunchKernelGGL((k_persistent<1, K0, K1, K2, RK>), dim3(blocks), dim3(256), 0, s,
-                               c->sys, P, M, c->d_counter, refill_min, check_every, st->d,
+                               c->sys, P, M, counter, refill_min, check_every, st->d,
                                st->nstep, st->nrej, st->status, st->ld);
     }
 };
@@ -1035,6 +1037,19 @@ int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qca
             return fail(nullptr, QCAMS_EHIP, "hipSetDevice(%d): %s", device, hipGetErrorString(e));
         }
     }
+    {
+        // the compute-unit count and the events around the persistent launch
+        int cu = 0;
+        hipError_t e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device);
+        c->n_cu = cu > 0 ? cu : 256;
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev_prop[k]);
+        if (e != hipSuccess) {
+            for (int k = 0; k < 2; ++k)
+                if (c->ev_prop[k]) (void)hipEventDestroy(c->ev_prop[k]);
+            delete c;
+            return fail(nullptr, QCAMS_EHIP, "device set-up: %s", hipGetErrorString(e));
+        }
+    }
     const double mA = sys->mass[0], mB = sys->mass[1], mC = sys->mass[2];
     Sys& S = c->sys;
     for (int i = 0; i < 3; ++i) {
@@ -1064,7 +1079,7 @@ int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qca
     if (hipMalloc(&d_sh, 3 * sizeof(Shape)) != hipSuccess ||
         hipMalloc(&d_rc, 3 * sizeof(int)) != hipSuccess) {
         (void)hipFree(d_sh);
-        delete c;
+        qcams_destroy(c);
         return fail(nullptr, QCAMS_ENOMEM, "device allocation failed");
     }
     hipLaunchKernelGGL(k_shapes, dim3(1), dim3(64), 0, 0, S.pot[0], S.pot[1], S.pot[2], d_sh,
@@ -1075,7 +1090,7 @@ int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qca
     (void)hipFree(d_sh);
     (void)hipFree(d_rc);
     if (e != hipSuccess) {
-        delete c;
+        qcams_destroy(c);
         return fail(nullptr, QCAMS_EHIP, "pair shapes: %s", hipGetErrorString(e));
     }
     for (int i = 0; i < 3; ++i) {
@@ -1084,7 +1099,7 @@ int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qca
             continue;
         }
         if (h_rc[i] != 0) {
-            delete c;
+            qcams_destroy(c);
             return fail(nullptr, QCAMS_EINVAL,
                         "pair %d: potential has no single well / barrier structure", i);
         }
@@ -1504,15 +1519,17 @@ int qcams_classify(qcams_ctx* c, const qcams_state* st, int64_t n, const qcams_o
     return QCAMS_OK;
 }
 
-// the two reduction kernels: partial sums per chunk, then per instance
+// the two reduction kernels: partial sums per chunk (rows of xpart), then
+// per instance
 static void launch_xsec(qcams_ctx* c, const qcams_outcome* out, const int64_t* ids,
-                        const double* weight, int64_t n, double* xs, double* hist, hipStream_t s)
+                        const double* weight, int64_t n, double* xs, double* hist, double* xpart,
+                        hipStream_t s)
 {
     hipLaunchKernelGGL(k_xsec_part, dim3((unsigned)c->n_xchunks), dim3(kRedThreads), 0, s, c->d_inst,
                        c->n_inst, c->d_xoff, out->label, out->vt, out->d, out->ld, ids, weight, n,
-                       c->d_xpart);
+                       xpart);
     hipLaunchKernelGGL(k_xsec, dim3(c->n_inst), dim3(kRedThreads), 0, s, c->d_inst, c->n_inst,
-                       c->d_xoff, c->d_xpart, c->sys.mu123, ids, n, xs, hist);
+                       c->d_xoff, (const double*)xpart, c->sys.mu123, ids, n, xs, hist);
 }
 
 int qcams_cross_sections(qcams_ctx* c, const qcams_outcome* out, const int64_t* ids,
@@ -1523,7 +1540,7 @@ int qcams_cross_sections(qcams_ctx* c, const qcams_outcome* out, const int64_t* 
     if (!out || !xs || n < 0 || (n > 0 && (!ids || !out->label || !out->vt || !out->d || out->ld < n)))
         return fail(c, QCAMS_EINVAL, "bad arguments");
     HIP_OK(c, hipSetDevice(c->device));
-    launch_xsec(c, out, ids, weight, n, xs, hist, (hipStream_t)stream);
+    launch_xsec(c, out, ids, weight, n, xs, hist, c->d_xpart, (hipStream_t)stream);
     HIP_OK(c, hipGetLastError());
     return QCAMS_OK;
 }
@@ -1555,25 +1572,36 @@ static int run_width(const qcams_ctx* c, const qcams_run_opts* o)
     return 1.5 * c->cost_max > 2.1 * c->cost_total / L ? 4 : 1;
 }
 
+// Device work buffers of one run: the work-list cursors and wave-step count
+// [kCounters], the work order [n_total], the reduction's per-chunk partial
+// sums [n_xchunks][kPartStride] (the context's own allocations).
+struct RunBufs {
+    unsigned long long* counter;
+    int64_t* order;
+    double* xpart;
+};
+
 // The run is three launch groups: the small set-up kernels (work order,
 // initial conditions, counter reset), the persistent propagation kernel, and
 // the small analysis kernels (classification, reduction).  In graph mode the
 // two small groups are captured and replayed; the persistent kernel is one
 // launch either way and is bracketed by HIP events for its duration.
-static void enqueue_pre(qcams_ctx* c, const qcams_run_opts* o, const qcams_state* st,
-                        double* sample, int64_t* ids, hipStream_t s)
+static void enqueue_pre(qcams_ctx* c, const qcams_run_opts* o, const RunBufs& B,
+                        const qcams_state* st, double* sample, int64_t* ids, hipStream_t s)
 {
     const int64_t n = c->n_total;
     const bool lpt = o->lpt != 0;
     hipLaunchKernelGGL(k_run_tables, dim3(grid_of(n, 256)), dim3(256), 0, s, c->d_inst, c->n_inst,
                        lpt ? c->d_lpt_inst : c->d_id_inst, lpt ? c->d_lpt_off : c->d_nat_off,
-                       c->d_nat_off, n, ids, c->d_order);
+                       c->d_nat_off, n, ids, B.order);
     dispatch_init(c, run_variant(c, o), ids, n, st, sample, s);
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, c->d_counter);
+    // a fill kernel, not a memset: the counters start at zero also in
+    // captured graphs
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, B.counter);
 }
 
-static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const qcams_state* st,
-                              hipStream_t s)
+static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const RunBufs& B,
+                              const qcams_state* st, hipStream_t s)
 {
     const int blocks = o->blocks > 0 ? o->blocks : c->n_cu;
     const int width = run_width(c, o);
@@ -1582,7 +1610,8 @@ static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const qcams
     const int ce = o->check_every < 1 ? 1 : o->check_every;
     if (hipEventRecord(c->ev_prop[0], s) != hipSuccess) return QCAMS_EHIP;
     with_variant<PersistentL>(c, run_variant(c, o), c, width, blocks, rm, ce,
-                              (const int64_t*)c->d_order, st, s);
+                              (const int64_t*)B.order, B.counter, st, s);
+    c->last_counter = B.counter;
     c->last_opts = *o;
     c->last_opts.blocks = blocks;
     c->last_opts.refill_min = rm;
@@ -1595,14 +1624,15 @@ static int enqueue_persistent(qcams_ctx* c, const qcams_run_opts* o, const qcams
     return hipGetLastError() == hipSuccess ? QCAMS_OK : QCAMS_EHIP;
 }
 
-static void enqueue_post(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out,
-                         int64_t* ids, double* sample, double* xs, double* hist, hipStream_t s)
+static void enqueue_post(qcams_ctx* c, const RunBufs& B, const qcams_state* st,
+                         const qcams_outcome* out, int64_t* ids, double* sample, double* xs,
+                         double* hist, hipStream_t s)
 {
     const int64_t n = c->n_total;
     hipLaunchKernelGGL(k_classify, dim3(grid_of(n, 128)), dim3(128), 0, s, c->sys, c->prm, st->d,
                        st->status, st->ld, n, out->label, out->vt, out->jt, out->d, out->ld);
     launch_xsec(c, out, ids, sample ? (const double*)(sample + 5 * st->ld) : (const double*)nullptr,
-                n, xs, hist, s);
+                n, xs, hist, B.xpart, s);
 }
 
 static int capture(qcams_ctx* c, hipGraph_t* g, hipGraphExec_t* x, const std::function<void(hipStream_t)>& f)
@@ -1620,28 +1650,40 @@ static int capture(qcams_ctx* c, hipGraph_t* g, hipGraphExec_t* x, const std::fu
     return QCAMS_OK;
 }
 
-int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, double* sample,
-              const qcams_outcome* out, int64_t* ids, double* xs, double* hist, void* stream)
+// Arguments of a run (qcams_run): buffers present and
+// large enough, options valid; *o receives the options with defaults.
+static int run_args(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st,
+                    const double* sample, const qcams_outcome* out, const int64_t* ids,
+                    const double* xs, qcams_run_opts* o)
 {
-    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
     if (c->n_inst < 1) return fail(c, QCAMS_EINVAL, "no instances installed");
     const int64_t n = c->n_total;
     if (int rc = check_state(c, st, n)) return rc;
     if (!out || !ids || !xs || (n > 0 && (!out->label || !out->vt || !out->jt || !out->d || out->ld < n)))
         return fail(c, QCAMS_EINVAL, "outcome / ids / xs buffers missing or too small");
-    qcams_run_opts o{};
-    o.blocks = 0;
-    o.refill_min = 1;
-    o.check_every = 8;
-    o.lpt = 1;
-    o.graph = 0;
-    if (opts) o = *opts;
-    if (o.blocks < 0 || o.refill_min < 0 || o.check_every < 0 || o.rk < 0 || o.rk > 2 ||
-        (o.lanes != 0 && o.lanes != 1 && o.lanes != 4 && o.lanes != 8))
+    *o = qcams_run_opts{};
+    o->blocks = 0;
+    o->refill_min = 1;
+    o->check_every = 8;
+    o->lpt = 1;
+    o->graph = 0;
+    if (opts) *o = *opts;
+    if (o->blocks < 0 || o->refill_min < 0 || o->check_every < 0 || o->rk < 0 || o->rk > 2 ||
+        (o->lanes != 0 && o->lanes != 1 && o->lanes != 4 && o->lanes != 8))
         return fail(c, QCAMS_EINVAL, "invalid run option");
     for (const Inst& I : c->h_inst)
         if (I.b_mode == 2 && (!sample || !c->d_prop_q))
             return fail(c, QCAMS_EINVAL, "proposal instances need a sample buffer and a proposal");
+    return QCAMS_OK;
+}
+
+int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, double* sample,
+              const qcams_outcome* out, int64_t* ids, double* xs, double* hist, void* stream)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    qcams_run_opts o;
+    if (int rc = run_args(c, opts, st, sample, out, ids, xs, &o)) return rc;
+    const int64_t n = c->n_total;
     HIP_OK(c, hipSetDevice(c->device));
     if (!c->d_counter) {
         if (hipMalloc(&c->d_counter, kCounters * sizeof(unsigned long long)) != hipSuccess) {
@@ -1668,36 +1710,40 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
         c->graph_key[0] = 0;
     }
     hipStream_t s = (hipStream_t)stream;
+    const RunBufs B{c->d_counter, c->d_order, c->d_xpart};
     if (!o.graph) {
-        enqueue_pre(c, &o, st, sample, ids, s);
-        if (enqueue_persistent(c, &o, st, s) != QCAMS_OK)
+        enqueue_pre(c, &o, B, st, sample, ids, s);
+        if (enqueue_persistent(c, &o, B, st, s) != QCAMS_OK)
             return fail(c, QCAMS_EHIP, "run launch: %s", hipGetErrorString(hipGetLastError()));
-        enqueue_post(c, st, out, ids, sample, xs, hist, s);
+        enqueue_post(c, B, st, out, ids, sample, xs, hist, s);
         HIP_OK(c, hipGetLastError());
         return QCAMS_OK;
     }
     // graph mode: capture the two small launch groups once per (buffers,
-    // options, instance table), replay them around the persistent launch
-    const uint64_t key[16] = {1,
+    // options, instance table, proposal tables), replay them around the
+    // persistent launch; the kernels read the tables' contents at replay
+    const uint64_t key[18] = {1,
                               (uint64_t)st->d, (uint64_t)st->nstep, (uint64_t)st->nrej,
                               (uint64_t)st->status, (uint64_t)st->ld, (uint64_t)sample,
                               (uint64_t)out->label, (uint64_t)out->d, (uint64_t)out->ld,
                               (uint64_t)ids, (uint64_t)xs, (uint64_t)hist,
                               (uint64_t)o.lpt | ((uint64_t)o.rk << 8) | ((uint64_t)c->n_xchunks << 16),
                               (uint64_t)out->vt ^ ((uint64_t)out->jt << 1),
-                              (uint64_t)c->n_total ^ ((uint64_t)c->n_inst << 40)};
+                              (uint64_t)c->n_total ^ ((uint64_t)c->n_inst << 40),
+                              (uint64_t)c->d_prop_q, (uint64_t)c->d_prop_cdf};
     if (memcmp(key, c->graph_key, sizeof key) != 0) {
         c->graph_key[0] = 0;
         int rc = capture(c, &c->graph, &c->graph_exec,
-                         [&](hipStream_t cs) { enqueue_pre(c, &o, st, sample, ids, cs); });
+                         [&](hipStream_t cs) { enqueue_pre(c, &o, B, st, sample, ids, cs); });
         if (rc == QCAMS_OK)
-            rc = capture(c, &c->graph2, &c->graph2_exec,
-                         [&](hipStream_t cs) { enqueue_post(c, st, out, ids, sample, xs, hist, cs); });
+            rc = capture(c, &c->graph2, &c->graph2_exec, [&](hipStream_t cs) {
+                enqueue_post(c, B, st, out, ids, sample, xs, hist, cs);
+            });
         if (rc != QCAMS_OK) return rc;
         memcpy(c->graph_key, key, sizeof key);
     }
     HIP_OK(c, hipGraphLaunch(c->graph_exec, s));
-    if (enqueue_persistent(c, &o, st, s) != QCAMS_OK)
+    if (enqueue_persistent(c, &o, B, st, s) != QCAMS_OK)
         return fail(c, QCAMS_EHIP, "run launch: %s", hipGetErrorString(hipGetLastError()));
     HIP_OK(c, hipGraphLaunch(c->graph2_exec, s));
     return QCAMS_OK;
@@ -1742,20 +1788,48 @@ static int tune_energy(qcams_ctx* c, const qcams_outcome* out, double* worst)
 }
 
 // Autotune results of this process, keyed by what decides them: the device,
-// the kernel specialisation, the tolerances and RK variant, the variant
-// search and its gate, and the size of the installed work.
+// the kernel specialisation, the variant search and its gate, the size of
+// the installed work, and a hash of everything else a run depends on -- the
+// system (masses, pair parameters and shapes), every integration parameter
+// and the installed instance table (energies, levels, impact parameters,
+// seeds, id ranges).  Two workloads of the same size but other content (which
+// may keep a different RK variant inside the energy gate) get their own
+// entries.
 struct TuneKey {
-    int device, kinds, lj126, search_rk, rk;
-    double atol, rtol, gate;
+    int device, kinds, lj126, search_rk;
+    double gate;
     int64_t n_total;
     int32_t n_inst;
+    uint64_t content;
     bool operator<(const TuneKey& o) const
     {
-        return std::tie(device, kinds, lj126, search_rk, rk, atol, rtol, gate, n_total, n_inst) <
-               std::tie(o.device, o.kinds, o.lj126, o.search_rk, o.rk, o.atol, o.rtol, o.gate,
-                        o.n_total, o.n_inst);
+        return std::tie(device, kinds, lj126, search_rk, gate, n_total, n_inst, content) <
+               std::tie(o.device, o.kinds, o.lj126, o.search_rk, o.gate, o.n_total, o.n_inst,
+                        o.content);
     }
 };
+
+// FNV-1a over raw bytes (the hashed structures are value-initialised, so
+// their padding is zero)
+static uint64_t fnv1a(uint64_t h, const void* p, size_t n)
+{
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static uint64_t tune_content(const qcams_ctx* c)
+{
+    uint64_t h = 14695981039346656037ull;
+    h = fnv1a(h, &c->sys, sizeof c->sys);
+    h = fnv1a(h, &c->prm, sizeof c->prm);
+    h = fnv1a(h, &c->level_method, sizeof c->level_method);
+    if (!c->h_inst.empty()) h = fnv1a(h, c->h_inst.data(), c->h_inst.size() * sizeof(Inst));
+    return h;
+}
 struct TuneVal {
     qcams_run_opts opts;
     double ms;
@@ -1774,9 +1848,8 @@ int qcams_autotune(qcams_ctx* c, const qcams_state* st, const qcams_outcome* out
     if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
     if (!best) return fail(c, QCAMS_EINVAL, "null result");
     if (search_rk != 0 && search_rk != 1) return fail(c, QCAMS_EINVAL, "search_rk must be 0 or 1");
-    const TuneKey key{c->device, c->kinds, c->lj126 ? 1 : 0, search_rk, c->prm.rk,
-                      c->prm.atol, c->prm.rtol, search_rk ? energy_gate : 0.0, c->n_total,
-                      c->n_inst};
+    const TuneKey key{c->device, c->kinds, c->lj126 ? 1 : 0, search_rk,
+                      search_rk ? energy_gate : 0.0, c->n_total, c->n_inst, tune_content(c)};
     if (reps >= 0) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune.find(key);
@@ -1922,11 +1995,11 @@ int qcams_last_run_options(qcams_ctx* c, qcams_run_opts* used)
 int qcams_last_run_wave_steps(qcams_ctx* c, int64_t* wave_steps)
 {
     if (!c || !wave_steps) return fail(c, QCAMS_EINVAL, "null argument");
-    if (!c->has_run || !c->d_counter) return fail(c, QCAMS_EINVAL, "no run recorded");
+    if (!c->has_run || !c->last_counter) return fail(c, QCAMS_EINVAL, "no run recorded");
     HIP_OK(c, hipSetDevice(c->device));
     HIP_OK(c, hipEventSynchronize(c->ev_prop[1]));
     unsigned long long v = 0;
-    HIP_OK(c, hipMemcpy(&v, c->d_counter + kWaveSteps, sizeof v, hipMemcpyDeviceToHost));
+    HIP_OK(c, hipMemcpy(&v, c->last_counter + kWaveSteps, sizeof v, hipMemcpyDeviceToHost));
     *wave_steps = (int64_t)v;
     return QCAMS_OK;
 }

@@ -2,7 +2,7 @@
 Sec. 4 workflow, Eq. (18)-(19)): group structure; sigma, its error and the
 rate against the oracle's trapezoid rule on the same per-b probabilities
 (to rounding); and against the oracle's own runs on a subsample of every
-b value (within 4 combined standard errors)."""
+b value (within 3 combined standard errors)."""
 import math
 
 import numpy as np
@@ -72,15 +72,19 @@ def test_grid_sigma_matches_oracle_trapezoid(Q, torch, orc):
 
 
 def test_grid_sigma_statistical_vs_oracle(Q, torch, orc):
-    """GPU grid sigma from 256 trajectories per b against the oracle's grid
-    sigma from every 8th of them (32 per b), per E_c and channel.  The
-    oracle's per-b errors use two pseudo-events (Agresti-Coull), so that a
-    channel it happens not to see at 32 draws per b keeps a nonzero error."""
-    wl, ctx, xs, grid = _grid_run(Q, torch, 256)
+    """GPU grid sigma from 1024 trajectories per b against the oracle's grid
+    sigma from every 8th of them (128 per b), per E_c and channel, within 3
+    combined standard errors.  The oracle's per-b errors use two
+    pseudo-events (Agresti-Coull), so that a channel it happens not to see
+    at 128 draws per b keeps a nonzero error.  With 40 comparisons about
+    0.27 % lie beyond 3 SE by chance: at most the 99.9 % quantile of
+    Binomial(40, 0.0027) of them may, and none beyond 4.5."""
+    from scipy import stats
+    wl, ctx, xs, grid = _grid_run(Q, torch, 1024)
     per = [np.arange(I.first_id, I.first_id + I.n_traj, 8, dtype=np.int64) for I in wl.instances]
-    recs, which = orc.run_workload(wl, per, processes=8)
+    recs, which = orc.run_workload(wl, per, processes=16)
     ref = orc.cross_sections(wl, recs["label"], np.ones(len(recs)), which)
-    worst = 0.0
+    zs = []
     for g in range(10):
         rows = np.arange(20 * g, 20 * g + 20)
         b = np.array([wl.instances[k].b for k in rows])
@@ -91,8 +95,12 @@ def test_grid_sigma_statistical_vs_oracle(Q, torch, orc):
             s, _ = orc.sigma_from_grid(b, P, ref["dP"][rows, c])
             _, e = orc.sigma_from_grid(b, P, np.sqrt(pt * (1 - pt) / (m + 4.0)))
             comb = math.hypot(e, grid[g, Q.G_DSIGMA + c])
-            z = abs(s - grid[g, Q.G_SIGMA + c]) / comb
-            worst = max(worst, z)
-            assert z <= 4.0, (g, c, s, grid[g, Q.G_SIGMA + c], comb)
-    print("largest |z| over 40 (E_c, channel) pairs: %.2f" % worst)
+            zs.append((abs(s - grid[g, Q.G_SIGMA + c]) / comb, g, c, s, grid[g, Q.G_SIGMA + c]))
+    z = np.array([q[0] for q in zs])
+    allowed = int(stats.binom.ppf(0.999, len(z), 0.0027))
+    beyond = [q for q in zs if q[0] > 3.0]
+    print("largest |z| over %d (E_c, channel) pairs: %.2f; %d beyond 3 SE (allowed %d)"
+          % (len(z), z.max(), len(beyond), allowed))
     print("sigma_q by E_c:", grid[:, Q.G_SIGMA])
+    assert len(beyond) <= allowed, beyond
+    assert z.max() <= 4.5, max(zs)

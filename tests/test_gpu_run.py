@@ -187,6 +187,35 @@ def test_graph_replays_match_eager(Q, torch):
         _same(ref, _snapshot(buf))
 
 
+def test_graph_switch_from_area_to_proposal_sampling(Q, torch):
+    """One context, graph mode: a run with area-sampled instances is captured
+    before any proposal table exists; then a proposal is installed and
+    instances of the same sizes switch to proposal sampling.  The replayed
+    run must use the proposal (it equals the eager run on the same context,
+    and no trajectory is failed for a missing table)."""
+    wl = _mixed_energy_workload(per=64)
+    ctx = Q.Context(wl.system, wl.params)
+    ctx.set_instances(wl.instances)
+    buf = ctx.new_run_buffers()
+    ctx.run(buf, Q.RunOpts(graph=1, refill_min=1, check_every=4, lpt=1))
+    torch.cuda.synchronize()
+    assert np.all(buf["outcome"].label.cpu().numpy() != Q.FAILED)
+    q = np.ones(Q.PROP_CELLS)
+    q[:1024] *= 8.0
+    ctx.proposal_set(q)
+    prop = [W.Instance(i.Ec_K, i.v, i.j, i.n_traj, i.first_id, i.seed, W.B_PROPOSAL, 0.0, i.bmax)
+            for i in wl.instances]
+    ctx.set_instances(prop)
+    ctx.run(buf, Q.RunOpts(graph=1, refill_min=1, check_every=4, lpt=1))
+    torch.cuda.synchronize()
+    got = _snapshot(buf)
+    assert np.all(got["label"] != Q.FAILED)
+    assert np.any(got["sample"][5] != 1.0)      # weights of the proposal
+    ctx.run(buf, Q.RunOpts(graph=0, refill_min=1, check_every=4, lpt=1))
+    torch.cuda.synchronize()
+    _same(got, _snapshot(buf))
+
+
 @pytest.mark.parametrize("search_rk", [False, True], ids=["schedule", "schedule_and_variant"])
 def test_autotune_returns_valid_options(Q, torch, search_rk):
     wl = _mixed_energy_workload(per=32)
@@ -225,6 +254,29 @@ def test_autotune_cache(Q, torch):
     assert ms3 != ms1 and b3.lanes in (1, 4, 8)
     b4, ms4 = ctx.autotune(buf, reps=1)
     assert b4.as_dict() == b3.as_dict() and ms4 == ms3
+
+
+def test_autotune_cache_is_keyed_on_content(Q, torch):
+    """Two workloads with the same numbers of instances and trajectories but
+    different content (slow 1e3 K against fast 1e5 K collisions): the second
+    is tuned on its own (its time is not the first one's cached time), and
+    asking again returns its own cached entry."""
+    def wl_at(Ec):
+        inst = [W.Instance(Ec, v, 0, 96, 96 * k, 31337, W.B_AREA, 0.0, 8.0)
+                for k, v in enumerate((0, 2, 4))]
+        return W.Workload("tune_%g" % Ec, W.h2ca_system(), W.Params(), inst)
+    res = {}
+    for Ec in (1e5, 1e3):
+        wl = wl_at(Ec)
+        ctx = Q.Context(wl.system, wl.params)
+        ctx.set_instances(wl.instances)
+        buf = ctx.new_run_buffers()
+        b, ms = ctx.autotune(buf, reps=1)
+        b2, ms2 = ctx.autotune(buf, reps=1)
+        assert b.as_dict() == b2.as_dict() and ms == ms2
+        res[Ec] = ms
+    print("autotuned ms: 1e5 K %.3f, 1e3 K %.3f" % (res[1e5], res[1e3]))
+    assert res[1e3] > 2.0 * res[1e5]
 
 
 def test_variant_override_equals_context_variant(Q, torch):
@@ -373,42 +425,73 @@ def _full_size_run(Q, torch, orc, wl, n_expect, seed):
     return lab, ids, xs
 
 
-def _pooled_channels_vs_oracle(orc, wl, xs, n, per):
-    """Per-channel probabilities pooled over instances (every instance holds
-    the same number of trajectories, so the pooled value is the mean of the
-    per-instance ones): the GPU's full run against the oracle's on a
-    stratified subsample, within 3 combined standard errors."""
-    recs, w2 = orc.run_workload(wl, per, processes=8)
+def _per_energy_channels_vs_oracle(orc, wl, xs, per_inst):
+    """Eq. (16), (18): per collision energy and channel, the GPU's full run
+    against the oracle's on a stratified subsample (the same number of ids
+    from every instance, so both sides weight the (v, j) instances of an
+    energy equally).  z = |P_gpu - P_oracle| / combined SE, with the GPU's
+    binomial SE over its full sample and the oracle's Agresti-Coull SE (two
+    pseudo-events, so a channel it happens not to see keeps a nonzero
+    error).  The bar is 3 combined SE for each cross section; with K
+    comparisons, about 0.27 % of them lie beyond 3 SE by chance, so the
+    number beyond 3 may not exceed the 99.9 % quantile of Binomial(K,
+    0.0027), none may exceed 4.5, and the channels pooled over all energies
+    must be within 3 SE."""
+    per = [np.arange(I.first_id, I.first_id + I.n_traj, I.n_traj // per_inst,
+                     dtype=np.int64)[:per_inst] for I in wl.instances]
+    recs, w2 = orc.run_workload(wl, per, processes=16)
     ref = orc.cross_sections(wl, recs["label"], np.ones(len(recs)), w2)
-    m = np.array([len(p) for p in per])
+    ecs = np.array([I.Ec_K for I in wl.instances])
+    ng = xs[:, 0]
+    zs = []
+    for E in np.unique(ecs):
+        rows = np.nonzero(ecs == E)[0]
+        n_g = ng[rows].sum()
+        m = per_inst * len(rows)
+        for ch in range(4):
+            p_g = (xs[rows, 7 + ch] * ng[rows]).sum() / n_g
+            x_o = float((ref["P"][rows, ch] * per_inst).sum())
+            p_o = x_o / m
+            pt = (x_o + 2.0) / (m + 4.0)
+            se = math.sqrt(p_g * (1 - p_g) / n_g + pt * (1 - pt) / (m + 4.0))
+            zs.append((abs(p_g - p_o) / se, E, ch, p_g, p_o))
+    z = np.array([q[0] for q in zs])
+    K = len(z)
+    allowed = int(stats.binom.ppf(0.999, K, 0.0027))
+    beyond = [q for q in zs if q[0] > 3.0]
+    print("%d (E_c, channel) comparisons: largest z %.2f, %d beyond 3 SE (allowed %d)"
+          % (K, z.max(), len(beyond), allowed))
+    assert len(beyond) <= allowed, beyond
+    assert z.max() <= 4.5, max(zs)
+    n = ng.sum()
+    m = per_inst * len(wl.instances)
     for ch in range(4):
-        p_g = xs[:, 7 + ch].mean()
-        p_o = (ref["P"][:, ch] * m).sum() / m.sum()
-        se = math.sqrt(max(p_g * (1 - p_g), 1e-12) / n + max(p_o * (1 - p_o), 1e-12) / m.sum())
+        p_g = (xs[:, 7 + ch] * ng).sum() / n
+        p_o = float((ref["P"][:, ch] * per_inst).sum()) / m
+        pt = (p_o * m + 2.0) / (m + 4.0)
+        se = math.sqrt(p_g * (1 - p_g) / n + pt * (1 - pt) / (m + 4.0))
         assert abs(p_g - p_o) <= 3 * se, (ch, p_g, p_o, se)
-    print("pooled P gpu", xs[:, 7:11].mean(axis=0), "oracle subsample",
-          (ref["P"] * m[:, None]).sum(axis=0) / m.sum(), "oracle trajectories", m.sum())
+    print("pooled P gpu", (xs[:, 7:11] * ng[:, None]).sum(axis=0) / n, "oracle subsample",
+          (ref["P"] * per_inst).sum(axis=0) / m, "oracle trajectories", m)
 
 
 def test_full_size_mixed_configuration(Q, torch, orc):
     """The 1,001,088-trajectory mixed-potential workload (generalized LJ 12-6,
     Morse, Buckingham; 2112 instances) at full size in the benchmark's launch
-    configuration: the checks of _full_size_run, then pooled channel
-    probabilities against the oracle on one id from every instance."""
+    configuration: the checks of _full_size_run, then the channel
+    probabilities per collision energy against the oracle on two ids from
+    every instance (4224 trajectories)."""
     wl = W.config_mixed()
     lab, ids, xs = _full_size_run(Q, torch, orc, wl, 1001088, seed=11)
-    per = [np.array([I.first_id + (k * 37) % I.n_traj], dtype=np.int64)
-           for k, I in enumerate(wl.instances)]
-    _pooled_channels_vs_oracle(orc, wl, xs, len(ids), per)
+    _per_energy_channels_vs_oracle(orc, wl, xs, per_inst=2)
 
 
 def test_full_size_sweep_configuration(Q, torch, orc):
     """The 10,005,248-trajectory sweep (64 collision energies x v 0-10 x
     j 0-10, 7744 instances) at full size in the benchmark's launch
-    configuration: the checks of _full_size_run, then pooled channel
-    probabilities against the oracle on one id from every instance."""
+    configuration: the checks of _full_size_run, then the channel
+    probabilities per collision energy against the oracle on two ids from
+    every instance (15,488 trajectories)."""
     wl = W.config_sweep()
     lab, ids, xs = _full_size_run(Q, torch, orc, wl, 10005248, seed=13)
-    per = [np.array([I.first_id + (k * 53) % I.n_traj], dtype=np.int64)
-           for k, I in enumerate(wl.instances)]
-    _pooled_channels_vs_oracle(orc, wl, xs, len(ids), per)
+    _per_energy_channels_vs_oracle(orc, wl, xs, per_inst=2)
