@@ -325,6 +325,29 @@ typedef struct {
 int qcams_run(qcams_ctx *ctx, const qcams_run_opts *opts, const qcams_state *st, double *sample,
               const qcams_outcome *out, int64_t *ids, double *xs, double *hist, void *stream);
 
+/* qcams_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same per-trajectory and per-instance results as
+ * qcams_run with graph = 0, but the run's work buffers (work-list counters,
+ * work order, the reduction's per-chunk partial sums) live in a static
+ * device array of 30,408,960 bytes that every GPU the library runs on holds
+ * until the process ends; the call itself makes no hipMalloc, hipFree or
+ * other allocating call.  Limits: at most 2,097,152 installed trajectories
+ * and 8,192 reduction chunks (one per started 4096 trajectories of each
+ * instance).  Every call on a GPU shares that GPU's array and leaves the
+ * last run's contents in it (the counters are cleared by a kernel at the
+ * start of each run): calls that overlap on one GPU -- on different streams
+ * or from different contexts -- race and must be serialised by the caller.
+ * The installed instance tables (qcams_set_instances) and the caller's
+ * buffers are as for qcams_run; opts->graph must be 0.
+ * qcams_last_run_kernel_ms, _wave_steps and _options report this run as
+ * they do for qcams_run (the wave-step count until the next run on the
+ * device overwrites the array).  async.  Errors: EINVAL (also beyond the
+ * limits or with graph set), EHIP. */
+int qcams_run_noalloc(qcams_ctx *ctx, const qcams_run_opts *opts, const qcams_state *st,
+                      double *sample, const qcams_outcome *out, int64_t *ids, double *xs,
+                      double *hist, void *stream);
+
 /* Duration in milliseconds of the persistent propagation kernel of the last
  * qcams_run on this context, from HIP events recorded around that launch on
  * the run's stream (also when the run was a graph replay).  Waits for the

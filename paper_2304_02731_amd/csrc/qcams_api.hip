@@ -50,7 +50,7 @@ struct qcams_ctx {
     double* d_xpart = nullptr;    // [n_xchunks][kPartStride]
     int64_t n_xchunks = 0, xoff_cap = 0, xpart_cap = 0;
     hipEvent_t ev_prop[2] = {nullptr, nullptr};   // around the persistent launch
-    unsigned long long* last_counter = nullptr;   // counters of the last run
+    unsigned long long* last_counter = nullptr;   // counters of the last run (context or scratch)
     qcams_run_opts last_opts{};                   // effective options of the last run
     bool lj126 = false;                           // pair AB is LJ 12-6
     double cost_max = 0.0, cost_total = 0.0;      // expected steps: largest, summed
@@ -645,6 +645,49 @@ constexpr int64_t kXChunk = 4096;
 constexpr int kPartHist = 3 * QCAMS_VMAX;     // (channel q, r1, r2) x v_t
 constexpr int kPartStride = 16 + kPartHist;   // 16 sums, then the histogram
 
+// ---------------------------------------------------------------------------
+// Static scratch of the run without allocation (qcams_run_noalloc): the
+// work-list counters, the work order and the reduction's partial sums of one
+// run live in this file-scope device array, one copy per GPU (held until the
+// process ends).  Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol): each device's address is
+// taken once with hipGetSymbolAddress, with that device current, when the
+// first context on it is created, and kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------
+constexpr int64_t kScratchItems = int64_t(1) << 21;   // trajectories per run
+constexpr int64_t kScratchChunks = 8192;              // reduction chunks per run
+constexpr size_t kScratchCounterBytes = 256;
+constexpr size_t kScratchOrderOff = kScratchCounterBytes;
+constexpr size_t kScratchPartOff = kScratchOrderOff + (size_t)kScratchItems * sizeof(int64_t);
+constexpr size_t kScratchBytes = kScratchPartOff + (size_t)kScratchChunks * kPartStride * sizeof(double);
+static_assert(kCounters * sizeof(unsigned long long) <= kScratchCounterBytes, "counter block");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on `device` (which must be current), taken once.
+static hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = (unsigned char*)ptr;
+    return hipSuccess;
+}
+
+static unsigned char* scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 __device__ inline int instance_of_chunk(const int64_t* xoff, int n_inst, int64_t blk)
 {
     int lo = 0, hi = n_inst - 1, k = 0;
@@ -1038,9 +1081,11 @@ int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qca
         }
     }
     {
-        // the compute-unit count and the events around the persistent launch
+        // per device, once: the static scratch of qcams_run_noalloc, the
+        // compute-unit count and the events around the persistent launch
+        hipError_t e = scratch_setup(device);
         int cu = 0;
-        hipError_t e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device);
         c->n_cu = cu > 0 ? cu : 256;
         for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev_prop[k]);
         if (e != hipSuccess) {
@@ -1574,7 +1619,8 @@ static int run_width(const qcams_ctx* c, const qcams_run_opts* o)
 
 // Device work buffers of one run: the work-list cursors and wave-step count
 // [kCounters], the work order [n_total], the reduction's per-chunk partial
-// sums [n_xchunks][kPartStride] (the context's own allocations).
+// sums [n_xchunks][kPartStride].  qcams_run uses the context's own
+// allocations; qcams_run_noalloc the device's static scratch array.
 struct RunBufs {
     unsigned long long* counter;
     int64_t* order;
@@ -1650,7 +1696,7 @@ static int capture(qcams_ctx* c, hipGraph_t* g, hipGraphExec_t* x, const std::fu
     return QCAMS_OK;
 }
 
-// Arguments of a run (qcams_run): buffers present and
+// Arguments of a run (qcams_run, qcams_run_noalloc): buffers present and
 // large enough, options valid; *o receives the options with defaults.
 static int run_args(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st,
                     const double* sample, const qcams_outcome* out, const int64_t* ids,
@@ -1746,6 +1792,34 @@ int qcams_run(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st, d
     if (enqueue_persistent(c, &o, B, st, s) != QCAMS_OK)
         return fail(c, QCAMS_EHIP, "run launch: %s", hipGetErrorString(hipGetLastError()));
     HIP_OK(c, hipGraphLaunch(c->graph2_exec, s));
+    return QCAMS_OK;
+}
+
+int qcams_run_noalloc(qcams_ctx* c, const qcams_run_opts* opts, const qcams_state* st,
+                      double* sample, const qcams_outcome* out, int64_t* ids, double* xs,
+                      double* hist, void* stream)
+{
+    if (!c) return fail(nullptr, QCAMS_EINVAL, "null context");
+    qcams_run_opts o;
+    if (int rc = run_args(c, opts, st, sample, out, ids, xs, &o)) return rc;
+    if (o.graph) return fail(c, QCAMS_EINVAL, "graph mode captures graphs: use qcams_run");
+    if (c->n_total > kScratchItems)
+        return fail(c, QCAMS_EINVAL, "%lld trajectories exceed the static scratch limit of %lld",
+                    (long long)c->n_total, (long long)kScratchItems);
+    if (c->n_xchunks > kScratchChunks)
+        return fail(c, QCAMS_EINVAL, "%lld reduction chunks exceed the static scratch limit of %lld",
+                    (long long)c->n_xchunks, (long long)kScratchChunks);
+    unsigned char* base = scratch_of(c->device);
+    if (!base) return fail(c, QCAMS_EINVAL, "no static scratch on device %d", c->device);
+    HIP_OK(c, hipSetDevice(c->device));
+    const RunBufs B{(unsigned long long*)base, (int64_t*)(base + kScratchOrderOff),
+                    (double*)(base + kScratchPartOff)};
+    hipStream_t s = (hipStream_t)stream;
+    enqueue_pre(c, &o, B, st, sample, ids, s);
+    if (enqueue_persistent(c, &o, B, st, s) != QCAMS_OK)
+        return fail(c, QCAMS_EHIP, "run launch: %s", hipGetErrorString(hipGetLastError()));
+    enqueue_post(c, B, st, out, ids, sample, xs, hist, s);
+    HIP_OK(c, hipGetLastError());
     return QCAMS_OK;
 }
 

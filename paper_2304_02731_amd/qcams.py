@@ -121,6 +121,8 @@ def lib():
     L.qcams_cross_sections.argtypes = [vp, C.POINTER(OutcomeC), vp, vp, i64, vp, vp, vp]
     L.qcams_run.argtypes = [vp, C.POINTER(RunOpts), C.POINTER(StateC), vp, C.POINTER(OutcomeC),
                             vp, vp, vp, vp]
+    L.qcams_run_noalloc.argtypes = [vp, C.POINTER(RunOpts), C.POINTER(StateC), vp,
+                                    C.POINTER(OutcomeC), vp, vp, vp, vp]
     L.qcams_last_run_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
     L.qcams_last_run_wave_steps.argtypes = [vp, C.POINTER(C.c_int64)]
     L.qcams_last_run_options.argtypes = [vp, C.POINTER(RunOpts)]
@@ -385,6 +387,18 @@ class Context:
             buf["sample"].data_ptr() if with_sample else None, C.byref(out.c()),
             buf["ids"].data_ptr(), buf["xs"].data_ptr(),
             buf["hist"].data_ptr() if with_hist else None, _stream(stream)), "qcams_run")
+        return buf["xs"], buf["hist"]
+
+    def run_noalloc(self, buf, opts: Optional[RunOpts] = None, stream=None, with_sample=True,
+                    with_hist=True):
+        """qcams_run_noalloc: the fused run with its work buffers in the
+        library's static device scratch (no allocation in the call)."""
+        st, out = buf["state"], buf["outcome"]
+        self._check(lib().qcams_run_noalloc(
+            self._h, C.byref(opts) if opts is not None else None, C.byref(st.c()),
+            buf["sample"].data_ptr() if with_sample else None, C.byref(out.c()),
+            buf["ids"].data_ptr(), buf["xs"].data_ptr(),
+            buf["hist"].data_ptr() if with_hist else None, _stream(stream)), "qcams_run_noalloc")
         return buf["xs"], buf["hist"]
 
     def last_run_kernel_ms(self) -> float:
