@@ -59,7 +59,7 @@ KINDS = {"morse": "0,0,0", "mixed": "3,0,2"}   # 3: LJ 12-6 specialisation
 # workload -> (surface, CPU-baseline stride of the process pool, of one core)
 WORKLOADS = {"sweep": ("morse", 1000, 10000), "batched": ("morse", 2, 50),
              "small": ("morse", 1, 5), "mixed": ("mixed", 500, 5000),
-             "paper_grid": ("morse", 1000, 10000)}
+             "paper_grid": ("morse", 500, 5000)}
 PEAK_FP64_VECTOR = 78.6e12   # MI355X, FLOP/s
 STATUS_NAMES = ("running", "ok_rstop", "ok_tmax", "fail_maxsteps", "fail_nonfinite",
                 "fail_hmin", "collapse")
@@ -112,9 +112,16 @@ def parse():
 
 
 def _oracle_sample(wl, stride):
+    """Every stride-th trajectory of the workload, counted over all its
+    trajectories in instance order (a systematic sample spread over every
+    instance), as global ids per instance."""
     import numpy as np
-    return [np.arange(i.first_id, i.first_id + i.n_traj, stride, dtype=np.int64)
-            for i in wl.instances]
+    out, pos = [], 0
+    for i in wl.instances:
+        first = (-pos) % stride                  # first local index on the global stride
+        out.append(np.arange(i.first_id + first, i.first_id + i.n_traj, stride, dtype=np.int64))
+        pos += i.n_traj
+    return out
 
 
 def cpu_baseline(wl, stride_pool, stride_one, procs):
@@ -138,12 +145,12 @@ def cpu_baseline(wl, stride_pool, stride_one, procs):
     steps1 = int(recs1["nstep"].sum() + recs1["nrej"].sum())
     cpu = host_cpu()
     return {"value": n / dt, "unit": "trajectories/s", "cores": procs, "kind": "oracle",
-            "sample": "every %dth trajectory id of all %d instances (%d trajectories), serial C "
+            "sample": "every %dth trajectory over all %d instances (%d trajectories), serial C "
                       "oracle in a %d-process pool, %.1f s, on %s"
                       % (stride_pool, len(wl.instances), n, procs, dt, cpu),
             "one_core": {"trajectories_per_s": n1 / dt1, "ms_per_trajectory": 1e3 * dt1 / n1,
                          "trial_steps_per_s": steps1 / dt1,
-                         "sample": "every %dth trajectory id of all %d instances (%d "
+                         "sample": "every %dth trajectory over all %d instances (%d "
                                    "trajectories, %d trial steps), one process, %.1f s"
                                    % (stride_one, len(wl.instances), n1, steps1, dt1)}}
 

@@ -38,7 +38,7 @@ def test_without_gpu_the_bench_refuses_rather_than_falls_back():
 
 
 def test_cpu_baseline_leg_reports_the_contract_keys():
-    """The oracle timed on bounded stratified samples (here every 100th of
+    """The oracle timed on bounded systematic samples (here every 100th of
     the small workload's 500 trajectories in a one-process pool, and every
     250th on one core)."""
     import qcams_workloads as W
@@ -76,6 +76,20 @@ def test_roofline_tables_cover_every_workload_and_variant():
     for (wl, kernel), nbytes in B.TRAFFIC.items():
         assert wl in names and kernel.startswith("k_persistent<") and nbytes > 0
     assert B.PEAK_FP64_VECTOR == 78.6e12
+
+
+def test_oracle_sample_strides_over_all_trajectories():
+    """The sample takes every k-th trajectory counted across instances: one
+    id per k overall, spread over the instances in order."""
+    import numpy as np
+    import qcams_workloads as W
+    B = _bench()
+    wl = W.config_batched(per_inst=7)
+    per = B._oracle_sample(wl, 5)
+    ids = np.concatenate(per)
+    assert np.array_equal(ids, np.arange(0, wl.n_traj, 5))
+    for i, p in zip(wl.instances, per):
+        assert np.all((p >= i.first_id) & (p < i.first_id + i.n_traj))
 
 
 def test_outcomes_by_status_counts():
