@@ -14,7 +14,8 @@
  * Conventions for every call:
  *  - Units: atomic units (hbar = m_e = a0 = E_h = 1), except collision
  *    energies, which are given in kelvin (as the paper's input file does).
- *    Masses are in electron masses.
+ *    Masses are in electron masses or, with qcams_system.mass_unit =
+ *    QCAMS_MASS_AMU, in unified atomic mass units (converted by the library).
  *  - Return value: QCAMS_OK (0) or a negative QCAMS_E* code; qcams_last_error
  *    gives a message.  No exception or abort crosses the ABI.  Problems of a
  *    single trajectory are reported in its status / label, never as a call
@@ -60,6 +61,19 @@ extern "C" {
 #define QCAMS_MORSE 0 /* V = De (1 - exp(-alpha (r - re)))^2 - De;  p = {De, re, alpha} */
 #define QCAMS_LJ 1    /* V = Cn r^-n - Cm r^-m, integers n > m >= 3;  p = {Cn, Cm} */
 #define QCAMS_BUCK 2  /* V = A exp(-b r) - C6 r^-6;  p = {A, b, C6} */
+/* Input forms, converted by the library (qcams_system_resolve):
+ * QCAMS_MORSE_WE: the Morse pair by its harmonic frequency, as the paper's
+ *   input file gives it (keys de, re, we):  p = {De, re, w_e};
+ *   alpha = w_e sqrt(mu / (2 De)) with mu the pair's reduced mass.
+ * QCAMS_LJ_EPS: the LJ pair by the depth eps and position r_m of its
+ *   minimum, exponents n > m >= 3:  p = {eps, r_m};
+ *   Cn = eps m r_m^n / (n - m), Cm = eps n r_m^m / (n - m). */
+#define QCAMS_MORSE_WE 3
+#define QCAMS_LJ_EPS 4
+
+/* ---- mass units ---- */
+#define QCAMS_MASS_ME 0  /* electron masses */
+#define QCAMS_MASS_AMU 1 /* unified atomic mass units: 1 u = 1822.888486209 m_e (CODATA 2018) */
 
 /* ---- impact-parameter sampling ---- */
 #define QCAMS_B_FIXED 0    /* every trajectory at b */
@@ -84,15 +98,17 @@ extern "C" {
 #define QCAMS_FAILED 5     /* the trajectory did not end with OK_RSTOP / OK_TMAX */
 
 typedef struct {
-    int32_t kind; /* QCAMS_MORSE / QCAMS_LJ / QCAMS_BUCK */
+    int32_t kind; /* QCAMS_MORSE / QCAMS_LJ / QCAMS_BUCK / QCAMS_MORSE_WE / QCAMS_LJ_EPS */
     int32_t n, m; /* LJ exponents (n > m), ignored otherwise */
     int32_t pad;
     double p[6];  /* see the kind's comment; unused entries ignored */
 } qcams_pair;
 
 typedef struct {
-    double mass[3];     /* mA, mB, mC in electron masses; AB is the molecule */
+    double mass[3];     /* mA, mB, mC in mass_unit; AB is the molecule */
     qcams_pair pair[3]; /* AB, BC, CA */
+    int32_t mass_unit;  /* QCAMS_MASS_ME (0) or QCAMS_MASS_AMU */
+    int32_t pad;
 } qcams_system;
 
 typedef struct {
@@ -179,11 +195,20 @@ typedef struct {
 
 typedef struct qcams_ctx qcams_ctx;
 
-/* Create a context on `device` for one system and parameter set.  Finds the
- * pair shapes (Buckingham inner maximum, potential minimum, the maximum of
- * r^3 V') on the device.  sync.  Errors: EINVAL (bad masses, kinds, LJ
- * exponents, tolerances, a potential without the single-well shape),
- * EHIP, ENOMEM. */
+/* The system in its canonical form (Sec. 3.1 units, Sec. 3.2 pairs): masses
+ * converted to electron masses (mass_unit = QCAMS_MASS_ME on return) and the
+ * input forms QCAMS_MORSE_WE / QCAMS_LJ_EPS converted to QCAMS_MORSE /
+ * QCAMS_LJ as documented above; other pairs copied.  qcams_create applies
+ * the same conversion.  in, out: host (may alias).  Needs no device.
+ * Errors (message from qcams_last_error(NULL)): EINVAL (unknown unit or
+ * kind, non-positive masses, invalid pair parameters). */
+int qcams_system_resolve(const qcams_system *in, qcams_system *out);
+
+/* Create a context on `device` for one system and parameter set (the system
+ * resolved as by qcams_system_resolve).  Finds the pair shapes (Buckingham
+ * inner maximum, potential minimum, the maximum of r^3 V') on the device.
+ * sync.  Errors: EINVAL (bad masses, units, kinds, LJ exponents, tolerances,
+ * a potential without the single-well shape), EHIP, ENOMEM. */
 int qcams_create(qcams_ctx **ctx, int device, const qcams_system *sys,
                  const qcams_params *prm);
 

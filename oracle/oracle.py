@@ -155,12 +155,19 @@ KELVIN = 3.1668115634556e-6     # k_B in hartree per kelvin (CODATA 2018)
 KINDS = {"morse": 0, "lj": 1, "buck": 2}
 
 
-def make_pair(p: W.Pair) -> Pair:
+def make_pair(p: W.Pair, mu: float | None = None) -> Pair:
+    """The oracle's pair.  A Morse pair given by its harmonic frequency w_e
+    (the paper's input keys de, re, we) gets alpha = w_e sqrt(mu / (2 De))
+    with mu the pair's reduced mass (READING: the paper names the keys, not
+    the conversion; this is the harmonic limit of the Morse oscillator)."""
     q = Pair()
     q.kind = KINDS[p.kind]
     P = p.params
     if p.kind == "morse":
-        vals = [P["De"], P["re"], P["alpha"]]
+        if "alpha" in P:
+            vals = [P["De"], P["re"], P["alpha"]]
+        else:
+            vals = [P["De"], P["re"], P["we"] * math.sqrt(mu / (2.0 * P["De"]))]
     elif p.kind == "lj":
         n, m = int(P["n"]), int(P["m"])
         q.n, q.m = n, m
@@ -182,7 +189,8 @@ def make_system(s: W.System, masses_me: Sequence[float] | None = None) -> System
     m = masses_me if masses_me is not None else [x * AMU for x in s.masses_amu]
     for i in range(3):
         out.mass[i] = float(m[i])
-        out.pair[i] = make_pair(s.pairs[i])
+        ma, mb = float(m[i]), float(m[(i + 1) % 3])        # pair AB, BC, CA
+        out.pair[i] = make_pair(s.pairs[i], ma * mb / (ma + mb))
     return out
 
 

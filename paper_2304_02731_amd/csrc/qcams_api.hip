@@ -971,6 +971,59 @@ static bool pair_ok(const qcams_pair& p)
 
 static bool pot_is_zero(const qcams_pair& p) { return p.kind == QCAMS_MORSE && p.p[0] == 0.0; }
 
+// Units and reduced masses of the system (Sec. 3.1; Eq. (2)) and the pair
+// parameters of the input forms: masses in electron masses, Morse range from
+// the harmonic frequency, LJ coefficients from the depth and position of the
+// minimum.  Returns 0, or -1 with a message.
+static const double kAmuInMe = 1822.888486209;   // m_u / m_e, CODATA 2018
+static int resolve_system(const qcams_system* in, qcams_system* out, char* msg, size_t len)
+{
+    qcams_system r = *in;
+    if (in->mass_unit != QCAMS_MASS_ME && in->mass_unit != QCAMS_MASS_AMU) {
+        snprintf(msg, len, "unknown mass unit %d", in->mass_unit);
+        return -1;
+    }
+    for (int i = 0; i < 3; ++i) {
+        if (!(in->mass[i] > 0.0)) {
+            snprintf(msg, len, "mass %d must be > 0", i);
+            return -1;
+        }
+        r.mass[i] = in->mass_unit == QCAMS_MASS_AMU ? in->mass[i] * kAmuInMe : in->mass[i];
+    }
+    r.mass_unit = QCAMS_MASS_ME;
+    for (int i = 0; i < 3; ++i) {
+        qcams_pair& q = r.pair[i];
+        if (q.kind == QCAMS_MORSE_WE) {
+            // alpha = w_e sqrt(mu / (2 De)), mu the pair's reduced mass
+            const double ma = r.mass[i], mb = r.mass[(i + 1) % 3];
+            const double mu = 1.0 / (1.0 / ma + 1.0 / mb);
+            if (!(q.p[0] > 0.0) || !(q.p[2] > 0.0)) {
+                snprintf(msg, len, "pair %d: Morse needs De > 0 and w_e > 0", i);
+                return -1;
+            }
+            q.kind = QCAMS_MORSE;
+            q.p[2] = q.p[2] * sqrt(mu / (2.0 * q.p[0]));
+        } else if (q.kind == QCAMS_LJ_EPS) {
+            // depth eps at r_m: Cn = eps m r_m^n / (n - m), Cm = eps n r_m^m / (n - m)
+            const int n = q.n, m = q.m;
+            const double eps = q.p[0], rm = q.p[1];
+            if (!(n > m && m >= 3 && n <= 64) || !(eps > 0.0) || !(rm > 0.0)) {
+                snprintf(msg, len, "pair %d: LJ needs n > m >= 3, eps > 0, r_m > 0", i);
+                return -1;
+            }
+            q.kind = QCAMS_LJ;
+            q.p[0] = eps * m * pow(rm, n) / (n - m);
+            q.p[1] = eps * n * pow(rm, m) / (n - m);
+        }
+        if (!pair_ok(q)) {
+            snprintf(msg, len, "pair %d: unsupported kind or parameters", i);
+            return -1;
+        }
+    }
+    *out = r;
+    return 0;
+}
+
 // Kernels are specialised for the all-Morse and the LJ 12-6 / Morse /
 // Buckingham pair triples (other triples select the pair kind at run time)
 // and for the RK variant; `with_kinds` maps the context to the instantiation.
@@ -1055,15 +1108,25 @@ static void dispatch_init(qcams_ctx* c, int rk, const int64_t* ids, int64_t n,
 
 extern "C" {
 
-int qcams_create(qcams_ctx** out, int device, const qcams_system* sys, const qcams_params* prm)
+int qcams_system_resolve(const qcams_system* in, qcams_system* out)
 {
-    if (!out || !sys || !prm) return fail(nullptr, QCAMS_EINVAL, "null argument");
+    if (!in || !out) return fail(nullptr, QCAMS_EINVAL, "null argument");
+    char msg[256];
+    if (resolve_system(in, out, msg, sizeof msg) != 0) return fail(nullptr, QCAMS_EINVAL, "%s", msg);
+    return QCAMS_OK;
+}
+
+int qcams_create(qcams_ctx** out, int device, const qcams_system* sys_in, const qcams_params* prm)
+{
+    if (!out || !sys_in || !prm) return fail(nullptr, QCAMS_EINVAL, "null argument");
     *out = nullptr;
-    for (int i = 0; i < 3; ++i)
-        if (!(sys->mass[i] > 0.0)) return fail(nullptr, QCAMS_EINVAL, "mass %d must be > 0", i);
-    for (int i = 0; i < 3; ++i)
-        if (!pair_ok(sys->pair[i]))
-            return fail(nullptr, QCAMS_EINVAL, "pair %d: unsupported kind or parameters", i);
+    qcams_system resolved;
+    {
+        char msg[256];
+        if (resolve_system(sys_in, &resolved, msg, sizeof msg) != 0)
+            return fail(nullptr, QCAMS_EINVAL, "%s", msg);
+    }
+    const qcams_system* sys = &resolved;
     if (!(prm->atol > 0.0) || !(prm->rtol >= 0.0) || !(prm->t_stop > 0.0) || !(prm->r_stop > 0.0) ||
         !(prm->R0 > 0.0) || !(prm->gb_sigma > 0.0) || prm->max_steps < 1 ||
         prm->max_steps > 2147483647LL || (prm->fixed_step && !(prm->h_fixed > 0.0)) ||

@@ -22,7 +22,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "qcams.h")
 
 # ---- constants mirrored from include/qcams.h ----
 OK, EINVAL, EUNBOUND, ENOROOT, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
-MORSE, LJ, BUCK = 0, 1, 2
+MORSE, LJ, BUCK, MORSE_WE, LJ_EPS = 0, 1, 2, 3, 4
+MASS_ME, MASS_AMU = 0, 1
 B_FIXED, B_AREA, B_PROPOSAL = 0, 1, 2
 RK_DOPRI5, RK_DOP853 = 0, 1
 LEVELS_BS, LEVELS_DVR = 0, 1
@@ -37,8 +38,6 @@ XS_N, XS_COUNTS, XS_P, XS_DP, XS_SIGMA, XS_DSIGMA, XS_RATE, XS_WTOT, XS_SUMW, XS
 # columns of a fixed-b grid row
 G_EC, G_V, G_J, G_NB, G_BMAX, G_N, G_SIGMA, G_DSIGMA, G_RATE = 0, 1, 2, 3, 4, 5, 6, 10, 14
 
-# unit conversions of the binding (CODATA 2018)
-AMU_IN_ME = 1822.888486209
 KIND = {"morse": MORSE, "lj": LJ, "buck": BUCK}
 
 
@@ -52,7 +51,8 @@ class Pair(C.Structure):
 
 
 class System(C.Structure):
-    _fields_ = [("mass", C.c_double * 3), ("pair", Pair * 3)]
+    _fields_ = [("mass", C.c_double * 3), ("pair", Pair * 3), ("mass_unit", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -109,6 +109,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.qcams_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(System), C.POINTER(Params)]
+    L.qcams_system_resolve.argtypes = [C.POINTER(System), C.POINTER(System)]
     L.qcams_destroy.argtypes = [vp]
     L.qcams_destroy.restype = None
     L.qcams_last_error.argtypes = [vp]
@@ -154,27 +155,31 @@ def lib():
 
 
 # ---------------------------------------------------------------------------
-# conversions of workload descriptions (duck-typed: .masses_amu, .pairs with
-# .kind / .params; params objects with the qcams_params field names)
+# marshalling of workload descriptions into the ABI structures (duck-typed:
+# .masses_amu or explicit electron masses, .pairs with .kind / .params;
+# params objects with the qcams_params field names).  Values are copied as
+# given; the library converts units and input forms (qcams_system_resolve).
 # ---------------------------------------------------------------------------
 def make_pair(p) -> Pair:
     q = Pair()
     kind = p.kind if isinstance(p.kind, int) else KIND[p.kind]
-    q.kind = kind
     P = p.params
     if kind == MORSE:
-        vals = [P["De"], P["re"], P["alpha"]]
+        if "alpha" in P:
+            vals = [P["De"], P["re"], P["alpha"]]
+        else:                      # the paper's input form: harmonic frequency w_e
+            kind = MORSE_WE
+            vals = [P["De"], P["re"], P["we"]]
     elif kind == LJ:
-        n, m = int(P["n"]), int(P["m"])
-        q.n, q.m = n, m
+        q.n, q.m = int(P["n"]), int(P["m"])
         if "Cn" in P:
             vals = [P["Cn"], P["Cm"]]
-        else:
-            # depth eps at rm: Cn = eps m rm^n/(n-m), Cm = eps n rm^m/(n-m)
-            eps, rm = float(P["eps"]), float(P["rm"])
-            vals = [eps * m * rm ** n / (n - m), eps * n * rm ** m / (n - m)]
+        else:                      # depth eps and position rm of the minimum
+            kind = LJ_EPS
+            vals = [P["eps"], P["rm"]]
     else:
         vals = [P["A"], P["b"], P["C6"]]
+    q.kind = kind
     for i, v in enumerate(vals):
         q.p[i] = float(v)
     return q
@@ -182,11 +187,26 @@ def make_pair(p) -> Pair:
 
 def make_system(system, masses_me: Optional[Sequence[float]] = None) -> System:
     s = System()
-    m = masses_me if masses_me is not None else [x * AMU_IN_ME for x in system.masses_amu]
+    if masses_me is not None:
+        m, s.mass_unit = masses_me, MASS_ME
+    else:
+        m, s.mass_unit = system.masses_amu, MASS_AMU
     for i in range(3):
         s.mass[i] = float(m[i])
         s.pair[i] = make_pair(system.pairs[i])
     return s
+
+
+def resolve_system(system, masses_me: Optional[Sequence[float]] = None) -> System:
+    """The system in the library's canonical form (qcams_system_resolve):
+    electron masses, Morse / LJ / Buckingham parameters.  Needs no GPU."""
+    s = make_system(system, masses_me)
+    out = System()
+    rc = lib().qcams_system_resolve(C.byref(s), C.byref(out))
+    if rc != OK:
+        raise QcamsError("qcams_system_resolve failed (%d): %s"
+                         % (rc, lib().qcams_last_error(None).decode()))
+    return out
 
 
 def make_params(p) -> Params:
@@ -266,8 +286,6 @@ class Context:
             raise QcamsError("qcams_create failed (%d): %s" % (rc, L.qcams_last_error(None).decode()))
         self._h = h
         self.instances = []
-        masses = [self._sys.mass[i] for i in range(3)]
-        self.mu123 = 1.0 / (1.0 / masses[2] + 1.0 / (masses[0] + masses[1]))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -8,9 +8,10 @@ Input (Sec. 3.1, Listing 1): keys ``vi``, ``ji``, ``Ec (K)``, ``b``, ``r0``,
 the three families (Sec. 3.2): Morse {``de``, ``re``, ``we``}, generalized
 LJ {``m``, ``n``, ``cm``, ``cn``, ``re``}, Buckingham {``a``, ``b``, ``c6``,
 ``re``, ``max``}, and the DVR grid {``npts``, ``xmin``, ``xmax``}.  All in
-atomic units except the collision energy (kelvin).  The Morse range
-parameter follows from the harmonic frequency, alpha = w_e sqrt(mu / (2 D_e))
-with mu the pair's reduced mass.  The ``re`` and ``max`` guesses are kept
+atomic units except the collision energy (kelvin).  The Morse pairs are
+handed to the library by their harmonic frequency (the library takes the
+range parameter alpha = w_e sqrt(mu / (2 D_e)) with mu the pair's reduced
+mass, qcams_system_resolve).  The ``re`` and ``max`` guesses are kept
 but not needed: the library finds the pair shapes itself.  The DVR grid of
 pair AB serves when a run asks for DVR levels (``levels="dvr"``).  A null
 seed is replaced by one drawn from the operating system and reported.
@@ -21,8 +22,8 @@ count vector n_f, final state s_f = (v_t, w, j_t) ((0, 0, 0) unless exactly
 one pair is bound), final rho_1, rho_2, P_1, P_2, final time, and the random
 draws that recreate it.
 
-This module only reads, converts and writes; every trajectory runs in the
-library's kernels (``Context.run``).
+This module only reads and writes; every trajectory runs in the library's
+kernels (``Context.run``).
 """
 from __future__ import annotations
 
@@ -30,7 +31,6 @@ import argparse
 import csv
 import dataclasses
 import json
-import math
 import os
 from typing import Optional, Sequence
 
@@ -49,15 +49,10 @@ class Pair:
 
 @dataclasses.dataclass(frozen=True)
 class System:
-    """A system in electron masses (what the input file holds); masses_amu is
-    derived for interfaces that take atomic mass units."""
+    """A system in electron masses (what the input file holds)."""
     masses_me: tuple
     pairs: tuple
     name: str = "input file"
-
-    @property
-    def masses_amu(self):
-        return tuple(m / Q.AMU_IN_ME for m in self.masses_me)
 
 
 @dataclasses.dataclass
@@ -74,14 +69,9 @@ class Calc:
     guesses: dict             # per pair: re / max guesses (kept, unused)
 
 
-def _reduced(a: float, b: float) -> float:
-    return 1.0 / (1.0 / a + 1.0 / b)
-
-
-def _pair(kind: str, p: dict, mu: float) -> Pair:
+def _pair(kind: str, p: dict) -> Pair:
     if kind == "morse":
-        de, re, we = float(p["de"]), float(p["re"]), float(p["we"])
-        return Pair("morse", {"De": de, "re": re, "alpha": we * math.sqrt(mu / (2.0 * de))})
+        return Pair("morse", {"De": float(p["de"]), "re": float(p["re"]), "we": float(p["we"])})
     if kind == "lj":
         return Pair("lj", {"n": int(p["n"]), "m": int(p["m"]), "Cn": float(p["cn"]),
                            "Cm": float(p["cm"])})
@@ -102,12 +92,11 @@ def load_input(src) -> Calc:
             d = json.load(f)
     m = d["masses"]
     ma, mb, mc = float(m["ma"]), float(m["mb"]), float(m["mc"])
-    mus = {"AB": _reduced(ma, mb), "BC": _reduced(mb, mc), "CA": _reduced(mc, ma)}
     pairs, dvr, guesses = [], {}, {}
     for name in ("AB", "BC", "CA"):
         kind = d["potential_" + name]
         pp = d["potential_params"][name]
-        pairs.append(_pair(kind, pp[kind], mus[name]))
+        pairs.append(_pair(kind, pp[kind]))
         dvr[name] = {k: pp[k] for k in ("npts", "xmin", "xmax") if k in pp}
         guesses[name] = {k: pp[kind][k] for k in ("re", "max") if k in pp[kind]}
     ip = d.get("int_params", {})

@@ -62,6 +62,51 @@ int main(void) {
     assert [int(x) for x in lines[2].split()] == [Q.NF, Q.NS, Q.XS_STRIDE, Q.VMAX]
 
 
+def test_system_resolve_against_the_oracle(built):
+    """Row a1 through the C ABI, on the CPU: qcams_system_resolve converts
+    masses in atomic mass units to electron masses, the LJ pair given by its
+    depth and minimum (eps, r_m) to (Cn, Cm) and the Morse pair given by its
+    harmonic frequency to its range parameter, as the oracle's own
+    conversions do (CODATA 2018 mass unit; Sec. 3.1-3.2)."""
+    import oracle as orc
+    import qcams_workloads as W
+    mixed = W.mixed_system()
+    hh = W.Pair("morse", {"De": 0.1745, "re": 1.40, "we": 0.0200749568})
+    cah = W.Pair("morse", {"De": 0.0625, "re": 3.78, "alpha": 0.62})
+    h2ca_we = W.System((1.008, 1.008, 40.078), (hh, cah, hh), "H2+Ca, Morse by w_e")
+    for system in (mixed, W.h2ca_system(), h2ca_we):
+        r = Q.resolve_system(system)
+        o = orc.make_system(system)
+        assert r.mass_unit == Q.MASS_ME
+        for i in range(3):
+            assert r.mass[i] == pytest.approx(o.mass[i], rel=1e-15)
+            assert r.pair[i].kind == o.pair[i].kind
+            assert (r.pair[i].n, r.pair[i].m) == (o.pair[i].n, o.pair[i].m)
+            for k in range(3):
+                assert r.pair[i].p[k] == pytest.approx(o.pair[i].p[k], rel=1e-14), (i, k)
+    # the mixed surface's LJ 12-6 pair (eps 0.02, r_m 4): C12 = 335544.32, C6 = 163.84
+    r = Q.resolve_system(mixed)
+    assert r.pair[0].p[0] == pytest.approx(335544.32, rel=1e-15)
+    assert r.pair[0].p[1] == pytest.approx(163.84, rel=1e-15)
+    # electron masses pass through unchanged
+    r = Q.resolve_system(mixed, masses_me=[1.0, 2.0, 3.0])
+    assert list(r.mass) == [1.0, 2.0, 3.0]
+
+
+def test_system_resolve_rejects_bad_input(built):
+    import qcams_workloads as W
+    s = Q.make_system(W.h2ca_system())
+    s.mass_unit = 7
+    out = Q.System()
+    assert Q.lib().qcams_system_resolve(C.byref(s), C.byref(out)) == Q.EINVAL
+    assert b"unit" in Q.lib().qcams_last_error(None)
+    bad = W.System((1.0, 1.0, 1.0), (W.Pair("lj", {"n": 6, "m": 12, "eps": 0.1, "rm": 3.0}),) * 3)
+    with pytest.raises(Q.QcamsError, match="LJ"):
+        Q.resolve_system(bad)
+    with pytest.raises(Q.QcamsError, match="mass"):
+        Q.resolve_system(W.h2ca_system(), masses_me=[1.0, -2.0, 3.0])
+
+
 def test_header_documents_each_call():
     """Every declared entry point carries a comment block with its contract."""
     txt = open(os.path.join(ROOT, "include", "qcams.h")).read()

@@ -54,6 +54,22 @@ def test_morse_range_from_harmonic_frequency(orc):
     assert e0 == pytest.approx(0.5 * we - we * we / (16.0 * de) - de, rel=1e-10)
 
 
+def test_morse_pair_goes_to_the_library_by_harmonic_frequency():
+    """The binding hands the file's (de, re, we) over unchanged, as the
+    library's Morse input form; the library's conversion equals the
+    oracle's alpha = w_e sqrt(mu / (2 D_e)) with the pair's reduced mass."""
+    import oracle as orc
+    calc = IO.load_input(_listing1_input(seed=1))
+    g = json.load(open(GOLDEN))["AB"]["morse"]
+    q = Q.make_pair(calc.system.pairs[0])
+    assert (q.kind, q.p[0], q.p[1], q.p[2]) == (Q.MORSE_WE, g["de"], g["re"], g["we"])
+    r = Q.resolve_system(calc.system, masses_me=calc.system.masses_me)
+    o = orc.make_system(calc.system, masses_me=calc.system.masses_me)
+    for i in range(3):
+        assert r.pair[i].kind == Q.MORSE
+        assert r.pair[i].p[2] == pytest.approx(o.pair[i].p[2], rel=1e-15)
+
+
 def test_lj_and_buckingham_parameters():
     calc = IO.load_input(_listing1_input(seed=1, kinds=("lj", "buck", "morse")))
     g = json.load(open(GOLDEN))["AB"]
@@ -64,7 +80,7 @@ def test_lj_and_buckingham_parameters():
     q = Q.make_pair(lj)
     assert (q.kind, q.n, q.m, q.p[0], q.p[1]) == (Q.LJ, 12, 6, g["lj"]["cn"], g["lj"]["cm"])
     with pytest.raises(ValueError):
-        IO._pair("harmonic", {}, 1.0)
+        IO._pair("harmonic", {})
 
 
 def _fake_result():
