@@ -111,6 +111,8 @@ def lib():
         L.orc_propagate_log.argtypes = [C.POINTER(System), C.POINTER(Params), _dp, _dp,
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64), _dp,
                                         C.c_int64, C.POINTER(C.c_int64)]
+        L.orc_trial_error.argtypes = [C.POINTER(System), C.POINTER(Params), _dp, C.c_double]
+        L.orc_trial_error.restype = C.c_double
         L.orc_pair_bound.argtypes = [C.POINTER(Pair), C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_int, _dp, _dp]
         L.orc_gb_weight.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int)]
@@ -321,18 +323,25 @@ def propagate(sys: System, prm: Params, y, aux):
     return st, y, aux, ns.value, nr.value
 
 
-def propagate_log(sys: System, prm: Params, y, aux, log_cap: int = 1 << 20):
+def propagate_log(sys: System, prm: Params, y, aux, log_cap: int = 1 << 16):
     """propagate() with the record of its trials: returns (status, y, aux,
-    nstep, nrej, trials) with trials [n, 4] = (t, trial step, error norm,
-    accepted) in order (the first log_cap of them)."""
+    nstep, nrej, trials) with trials [n, 16] = (t, trial step, error norm,
+    accepted, the 12-component state the trial starts from) in order (the
+    first log_cap of them)."""
     y, py = _arr(np.array(y, dtype=np.float64, copy=True))
     aux, pa = _arr(np.array(aux, dtype=np.float64, copy=True))
     ns, nr, nl = C.c_int64(0), C.c_int64(0), C.c_int64(0)
-    log = np.zeros((log_cap, 4))
+    log = np.zeros((log_cap, 16))
     st = lib().orc_propagate_log(C.byref(sys), C.byref(prm), py, pa, C.byref(ns), C.byref(nr),
                                  log.ctypes.data_as(C.POINTER(C.c_double)), log_cap,
                                  C.byref(nl))
     return st, y, aux, ns.value, nr.value, log[:min(nl.value, log_cap)].copy()
+
+
+def trial_error(sys: System, prm: Params, y, h: float) -> float:
+    """Error norm of one adaptive trial of step h from state y."""
+    y, py = _arr(np.array(y, dtype=np.float64, copy=True))
+    return lib().orc_trial_error(C.byref(sys), C.byref(prm), py, h)
 
 
 def pair_bound(pair, mu, J2, E, r, literal=0):

@@ -769,6 +769,20 @@ static double initial_step(const orc_system *s, const double *y, const double *f
     return fmin(h, span);
 }
 
+/* Error norm of one adaptive trial step of size h from state y (the
+ * integrator of prm->rk), as the adaptive loop below evaluates it. */
+double orc_trial_error(const orc_system *s, const orc_params *prm, const double *y, double h)
+{
+    double f0[12], ynew[12], k7[12], e[12];
+    orc_rhs(s, y, f0);
+    if (prm->rk == 1) {
+        if (!d8_ready) return NAN;
+        return d8_step(s, y, f0, h, prm->atol, prm->rtol, ynew, k7);
+    }
+    dp_step(s, y, f0, h, ynew, k7, e);
+    return err_norm(y, ynew, e, prm->atol, prm->rtol);
+}
+
 /* Buckingham collapse radius of each pair (0 if none). */
 static void collapse_radii(const orc_system *s, double *rb)
 {
@@ -793,8 +807,9 @@ int orc_propagate(const orc_system *s, const orc_params *prm, double *y, double 
 }
 
 /* orc_propagate with a record of every trial step (test diagnostics):
- * log[4 k + 0..3] = (t, trial step size, error norm, 1 if accepted) of the
- * first log_cap trials, *log_n = the number of trials made. */
+ * log[16 k + 0..3] = (t, trial step size, error norm, 1 if accepted) and
+ * log[16 k + 4..15] = the state the trial starts from, for the first
+ * log_cap trials; *log_n = the number of trials made. */
 int orc_propagate_log(const orc_system *s, const orc_params *prm, double *y, double *aux,
                       int64_t *nstep, int64_t *nrej, double *log, int64_t log_cap,
                       int64_t *log_n)
@@ -826,10 +841,12 @@ int orc_propagate_log(const orc_system *s, const orc_params *prm, double *y, dou
         if (prm->fixed_step) err = 0.0;
         if (!isfinite(err)) err = INFINITY;
         if (log && ntrial < log_cap) {
-            log[4 * ntrial + 0] = t;
-            log[4 * ntrial + 1] = hs;
-            log[4 * ntrial + 2] = err;
-            log[4 * ntrial + 3] = err <= 1.0 ? 1.0 : 0.0;
+            double *rec = log + 16 * ntrial;
+            rec[0] = t;
+            rec[1] = hs;
+            rec[2] = err;
+            rec[3] = err <= 1.0 ? 1.0 : 0.0;
+            memcpy(rec + 4, y, sizeof y[0] * 12);
         }
         ++ntrial;
         if (err <= 1.0) {

@@ -129,62 +129,86 @@ def test_init_rejects_ids_outside_instances(Q, torch):
 
 
 # ----------------------------------------------------------------------------
+def _accepted_times(log, tmax):
+    """Times after each accepted trial of an oracle trial log (t = 0 first),
+    and the log rows of the accepted trials."""
+    acc = np.nonzero(log[:, 3] == 1.0)[0]
+    t, h = log[acc, 0], log[acc, 1]
+    return np.r_[0.0, np.where(h == tmax - t, tmax, t + h)], acc
+
+
+def _first_step_difference(log, tmax, gpu_times, rel=1e-3):
+    """Index (1-based) of the first accepted step whose size differs by more
+    than `rel` between the oracle's trial log and the GPU's accepted times,
+    or None."""
+    ot, _ = _accepted_times(log, tmax)
+    ho, hg = np.diff(ot), np.diff(np.asarray(gpu_times))
+    m = min(len(ho), len(hg))
+    d = np.nonzero(np.abs(hg[:m] / ho[:m] - 1.0) > rel)[0]
+    if len(d):
+        return int(d[0]) + 1
+    return None if len(ho) == len(hg) else m + 1
+
+
 def _short_horizon(Q, torch, orc, wl, ids, periods, **prm):
-    """GPU and oracle integrate the same initial states over a few periods.
-    Where both take the same steps (equal accepted and rejected counts) the
-    states agree to 1e-9 relative.  An accept/reject decision taken at an
-    error estimate within rounding of 1 can part the two step sequences;
-    then both are valid integrations at the tolerances and each is compared
-    with a tight-tolerance DOP853 reference: the GPU's error may not exceed
-    three times the largest error of the oracle over the sample (+1e-9)."""
+    """GPU and oracle integrate the same initial states over a few periods:
+    every final state agrees to 1e-9 relative, whatever the two step
+    sequences do.  The sequences are compared through the GPU's accepted
+    times (qcams_propagate_record, the same trajectory as qcams_propagate)
+    and the oracle's trial log, and the partings are reported: the
+    integrators' first trials take error estimates far below the rounding
+    level of the estimate (the starting step is small), where the kernels'
+    separable form and the oracle's plain form of the same estimate differ
+    by tens of per cent, so the step sizes differ from the first steps on;
+    such differences leave both integrations inside their tolerances, and
+    now and then change an accept/reject decision later on.  Fixed-step runs
+    must take identical steps."""
     ctx = _ctx(Q, wl, **prm)
     tid, st, smp = _gpu_init(Q, torch, ctx, ids)
     sys = orc.make_system(wl.system)
     p = dataclasses.replace(wl.params, **prm) if prm else wl.params
     oprm = orc.make_params(p)
-    tight = orc.make_params(dataclasses.replace(p, atol=1e-14, rtol=3e-14, rk=W.RK_DOP853))
     which = _inst_of(wl, ids)
     levs = {k: orc.level(sys, wl.instances[k].v, wl.instances[k].j) for k in set(which)}
     T = np.array([periods * levs[k][3] for k in which])
     st.d[Q.F_TMAX] = torch.as_tensor(T, device="cuda:0")
     st.d[Q.F_RSTOP].fill_(1e9)
-    ctx.propagate(st)
+    rec_max = 4096
+    rec, cnt = ctx.propagate_record(st, rec_max)
     torch.cuda.synchronize()
     d = st.d.cpu().numpy()
     status = st.status.cpu().numpy()
     nstep = st.nstep.cpu().numpy()
     nrej = st.nrej.cpu().numpy()
-    worst, parted = 0.0, []
+    rec, cnt = rec.cpu().numpy(), cnt.cpu().numpy()
+    worst, worst_parted, n_counts, first = 0.0, 0.0, 0, []
     for c, (i, k) in enumerate(zip(ids, which)):
         I = wl.instances[k]
         y0, aux, _ = orc.init(sys, oprm, orc.make_instance(I), levs[k], int(i))
         box = np.r_[0.0, T[c], 1e9, aux[3], aux[4], 0]
-        so, y, a, ns, nr = orc.propagate(sys, oprm, y0, box)
+        so, y, a, ns, nr, log = orc.propagate_log(sys, oprm, y0, box)
         assert status[c] == so == Q.OK_TMAX
         assert d[Q.F_T, c] == a[0] == T[c]
         rel = np.abs(d[:12, c] - y) / np.maximum(np.abs(y), 1.0)
-        if (nstep[c], nrej[c]) == (ns, nr):
-            worst = max(worst, rel.max())
-            assert rel.max() < 1e-9, (i, rel.max(), nstep[c], ns)
-        elif not p.fixed_step:
-            parted.append((c, i, y, rel.max(), (nstep[c], nrej[c], ns, nr)))
-        else:
-            raise AssertionError(("fixed-step counts differ", i, nstep[c], ns))
-    if parted:
-        e_orc, e_gpu = 0.0, []
-        for c, (i, k) in enumerate(zip(ids, which)):
-            I = wl.instances[k]
-            y0, aux, _ = orc.init(sys, oprm, orc.make_instance(I), levs[k], int(i))
-            box = np.r_[0.0, T[c], 1e9, aux[3], aux[4], 0]
-            _, yr, _, _, _ = orc.propagate(sys, tight, y0, box)
-            _, y, _, _, _ = orc.propagate(sys, oprm, y0, box)
-            scale = np.maximum(np.abs(yr), 1.0)
-            e_orc = max(e_orc, (np.abs(y - yr) / scale).max())
-            e_gpu.append((np.abs(d[:12, c] - yr) / scale).max())
-        for c, i, y, r, counts in parted:
-            assert e_gpu[c] <= 3 * e_orc + 1e-9, (i, e_gpu[c], e_orc, r, counts)
-        print("%d of %d step sequences parted; largest oracle error %.2e, GPU error on those %.2e"
-              % (len(parted), len(ids), e_orc, max(e_gpu[c] for c, *_ in parted)))
+        worst = max(worst, rel.max())
+        assert rel.max() < 1e-9, (i, rel.max(), (nstep[c], nrej[c], ns, nr))
+        assert cnt[c] == nstep[c] + 1 <= rec_max
+        k1 = _first_step_difference(log, T[c], rec[c, :cnt[c], 0])
+        same_counts = (nstep[c], nrej[c]) == (ns, nr)
+        if p.fixed_step:
+            assert k1 is None and same_counts, (i, nstep[c], ns)
+            continue
+        if not same_counts:
+            n_counts += 1
+            worst_parted = max(worst_parted, rel.max())
+        if k1 is not None:
+            first.append(k1)
+    print("%d trajectories: step counts differ for %d, a step size differs by more than 1e-3 "
+          "for %d (first at accepted step %s); largest relative difference of the final states "
+          "%.2e (%.2e where the counts differ)"
+          % (len(ids), n_counts, len(first),
+             "%d median / %d max" % (np.median(first), max(first)) if first else "-", worst,
+             worst_parted))
     return worst
 
 
