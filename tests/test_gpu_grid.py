@@ -74,11 +74,12 @@ def test_grid_sigma_matches_oracle_trapezoid(Q, torch, orc):
 def test_grid_sigma_statistical_vs_oracle(Q, torch, orc):
     """GPU grid sigma from 1024 trajectories per b against the oracle's grid
     sigma from every 8th of them (128 per b), per E_c and channel, within 3
-    combined standard errors.  The oracle's per-b errors use two
-    pseudo-events (Agresti-Coull), so that a channel it happens not to see
-    at 128 draws per b keeps a nonzero error.  With 40 comparisons about
-    0.27 % lie beyond 3 SE by chance: at most the 99.9 % quantile of
-    Binomial(40, 0.0027) of them may, and none beyond 4.5."""
+    standard errors of the difference: the trapezoid sum of the per-b
+    differences of P, each with the two-proportion variance of the pooled
+    per-b probability (the hypothesis that both sides estimate the same
+    P(b)).  With 40 comparisons about 0.27 % lie beyond 3 SE by chance: at
+    most the 99.9 % quantile of Binomial(40, 0.0027) of them may, and none
+    beyond 4.5."""
     from scipy import stats
     wl, ctx, xs, grid = _grid_run(Q, torch, 1024)
     per = [np.arange(I.first_id, I.first_id + I.n_traj, 8, dtype=np.int64) for I in wl.instances]
@@ -89,13 +90,21 @@ def test_grid_sigma_statistical_vs_oracle(Q, torch, orc):
         rows = np.arange(20 * g, 20 * g + 20)
         b = np.array([wl.instances[k].b for k in rows])
         m = np.array([len(per[k]) for k in rows], dtype=np.float64)
+        n = xs[rows, 0]
+        w = np.zeros_like(b)                     # trapezoid weights of the grid
+        w[1:] += 0.5 * np.diff(b)
+        w[:-1] += 0.5 * np.diff(b)
         for c in range(4):
-            P = ref["P"][rows, c]
-            pt = (P * m + 2.0) / (m + 4.0)
-            s, _ = orc.sigma_from_grid(b, P, ref["dP"][rows, c])
-            _, e = orc.sigma_from_grid(b, P, np.sqrt(pt * (1 - pt) / (m + 4.0)))
-            comb = math.hypot(e, grid[g, Q.G_DSIGMA + c])
-            zs.append((abs(s - grid[g, Q.G_SIGMA + c]) / comb, g, c, s, grid[g, Q.G_SIGMA + c]))
+            xg = xs[rows, 1 + c]
+            xo = ref["P"][rows, c] * m
+            s_o, _ = orc.sigma_from_grid(b, xo / m, np.zeros_like(b))
+            assert grid[g, Q.G_SIGMA + c] == pytest.approx(
+                2 * math.pi * float((w * b * xg / n).sum()), rel=1e-12, abs=1e-15)
+            pp = (xg + xo) / (n + m)
+            var = (2 * math.pi) ** 2 * float(((w * b) ** 2 * pp * (1 - pp) * (1 / n + 1 / m)).sum())
+            d = grid[g, Q.G_SIGMA + c] - s_o
+            zs.append((abs(d) / math.sqrt(var) if var > 0 else 0.0, g, c, s_o,
+                       grid[g, Q.G_SIGMA + c]))
     z = np.array([q[0] for q in zs])
     allowed = int(stats.binom.ppf(0.999, len(z), 0.0027))
     beyond = [q for q in zs if q[0] > 3.0]
