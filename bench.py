@@ -53,7 +53,8 @@ F_STEP = {("morse", 0): {"hand": 1850.0, "method": 1068.0, "counter": 1833.7},
 # WRITE_SIZE passes, scaled by the same counters on a plain copy of known
 # size (bench.py --probe copy), keyed by (workload, kernel); a kernel changed
 # since its counters were taken has no entry (null in the line).
-TRAFFIC = {("h2ca_sweep_7744inst_1e7", "k_persistent<1,0,0,0,1>"): 5.709e9}
+TRAFFIC = {("h2ca_sweep_7744inst_1e7", "k_persistent<1,0,0,0,1>"): 5.709e9,
+           ("h2ca_batched_96inst_1e5", "k_persistent<4,0,0,0,1>"): 3.286e7}
 RK_NAMES = {"dopri5": 0, "dop853": 1}
 KINDS = {"morse": "0,0,0", "mixed": "3,0,2"}   # 3: LJ 12-6 specialisation
 # workload -> (surface, CPU-baseline stride of the process pool, of one core)
