@@ -45,16 +45,18 @@ if ROOT not in sys.path:
 #           counted as one operation;
 #   counter the hardware FP64 counters (64 (ADD + MUL + TRANS + 2 FMA) per
 #           lane-step) of a full-wave fixed-step run of the one-lane kernel.
-F_STEP = {("morse", 0): {"hand": 1850.0, "method": 1068.0, "counter": 1833.7},
-          ("morse", 1): {"hand": 4000.0, "method": 2498.0, "counter": 3996.7},
-          ("mixed", 0): {"hand": 1754.0, "method": 1128.0, "counter": 1719.6},
-          ("mixed", 1): {"hand": 3808.0, "method": 2618.0, "counter": 3768.6}}
+F_STEP = {("morse", 0): {"hand": 1886.0, "method": 1068.0, "counter": 1869.7},
+          ("morse", 1): {"hand": 4072.0, "method": 2498.0, "counter": 4068.7},
+          ("mixed", 0): {"hand": 1778.0, "method": 1128.0, "counter": 1743.6},
+          ("mixed", 1): {"hand": 3856.0, "method": 2618.0, "counter": 3816.6}}
 # HBM bytes per launch of the persistent kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes, scaled by the same counters on a plain copy of known
 # size (bench.py --probe copy), keyed by (workload, kernel); a kernel changed
 # since its counters were taken has no entry (null in the line).
-TRAFFIC = {("h2ca_sweep_7744inst_1e7", "k_persistent<1,0,0,0,1>"): 5.709e9,
-           ("h2ca_batched_96inst_1e5", "k_persistent<4,0,0,0,1>"): 3.286e7}
+TRAFFIC = {("h2ca_sweep_7744inst_1e7", "k_persistent<1,0,0,0,1>"): 5.673e9,
+           ("h2ca_batched_96inst_1e5", "k_persistent<4,0,0,0,1>"): 3.242e7,
+           ("mixed_2112inst_1e6", "k_persistent<1,3,0,2,1>"): 5.748e8,
+           ("h2ca_paper_grid_v1j0", "k_persistent<1,0,0,0,1>"): 7.541e8}
 RK_NAMES = {"dopri5": 0, "dop853": 1}
 KINDS = {"morse": "0,0,0", "mixed": "3,0,2"}   # 3: LJ 12-6 specialisation
 # workload -> (surface, CPU-baseline stride of the process pool, of one core)
@@ -365,7 +367,8 @@ def main():
                      "flop_per_trial_step_method": fs["method"],
                      "frac_method": rate * fs["method"] / PEAK_FP64_VECTOR,
                      "flop_per_trial_step_counter": fs["counter"],
-                     "frac_counter": rate * fs["counter"] / PEAK_FP64_VECTOR},
+                     "frac_counter": (rate * fs["counter"] / PEAK_FP64_VECTOR
+                                      if fs["counter"] is not None else None)},
         "path": args.path, "run_opts": used.as_dict() if used else opts.as_dict(),
         "slots": slots,
         "autotune": tuned,

@@ -141,17 +141,22 @@ QD void sqrt_rsqrt(double s, double& r, double& ir)
 
 // e^x for x < 709: Cody-Waite reduction x = n ln2 + r, |r| <= ln2/2, with
 // ln2 split in a high part exact for |n| < 2^20 and a low correction, then a
-// degree-11 polynomial in Horner form, scaled by 2^n.  The polynomial
-// interpolates e^r at the 12 Chebyshev nodes of [-ln2/2, ln2/2] (solved in
-// 60-digit arithmetic, csrc/exp_poly.py); with its coefficients rounded to
-// double its relative error is below 1.7e-17, under the rounding of the
-// evaluation itself.
+// degree-11 polynomial in Horner form, scaled by 2^n.  n is the integer
+// nearest to x log2(e), formed by one FMA against 1.5 * 2^52: the sum's ulp
+// is 1, so the FMA rounds the exact product to an integer, and the low 32
+// bits of the sum hold n in two's complement (|n| < 2^31), which the scaling
+// takes directly.  The polynomial interpolates e^r at the 12 Chebyshev nodes
+// of [-ln2/2, ln2/2] (solved in 60-digit arithmetic, csrc/exp_poly.py); with
+// its coefficients rounded to double its relative error is below 1.7e-17,
+// under the rounding of the evaluation itself.
 QD double exp_cw(double x)
 {
     const double kLog2e = 1.4426950408889634074;
     const double kLn2Hi = 6.93147180369123816490e-01;
     const double kLn2Lo = 1.90821492927058770002e-10;
-    const double n = rint(x * kLog2e);
+    const double kShift = 6755399441055744.0;   // 1.5 * 2^52
+    const double t = fma(x, kLog2e, kShift);
+    const double n = t - kShift;
     double r = fma(-n, kLn2Hi, x);
     r = fma(-n, kLn2Lo, r);
     double p = 2.5110037605963777e-08;
@@ -166,7 +171,7 @@ QD double exp_cw(double x)
     p = fma(p, r, 0.5000000000000019);
     p = fma(p, r, 1.0);
     p = fma(p, r, 1.0);
-    return ldexp(p, (int)n);
+    return ldexp(p, (int)(unsigned)__builtin_bit_cast(unsigned long long, t));
 }
 
 // Step-size factor err^(-1/(q+1)) of the controller (q = 4 for the 5(4)
