@@ -102,15 +102,17 @@ def parse():
     ap.add_argument("--learned-replicates", type=int, default=96)
     ap.add_argument("--learned-n", type=int, default=200_000)
     ap.add_argument("--learned-epochs", type=int, default=20)
-    ap.add_argument("--probe", default="none", choices=["none", "flops", "copy"],
+    ap.add_argument("--probe", default="none", choices=["none", "flops", "copy", "mlp"],
                     help="counter-calibration runs instead of the benchmark: 'flops' integrates "
                          "every lane of full waves for a fixed number of fixed steps (FP64 "
                          "instruction counters per lane-step); 'copy' streams a buffer of "
-                         "known size (HBM byte counters)")
+                         "known size (HBM byte counters); 'mlp' times the proposal network's "
+                         "forward and gradient kernels at a large batch")
     ap.add_argument("--probe-lanes", type=int, default=256 * 1024)
     ap.add_argument("--probe-steps", type=int, default=300)
     ap.add_argument("--probe-h", type=float, default=0.5)
     ap.add_argument("--probe-mib", type=int, default=1024)
+    ap.add_argument("--probe-mlp-rows", type=int, default=1 << 20)
     return ap.parse_args()
 
 
@@ -215,6 +217,43 @@ def probe_copy(args, torch):
             "launches": 3}
 
 
+def probe_mlp(args, Q, torch):
+    """The proposal network's kernels at large batches: the forward pass on
+    probe_mlp_rows rows of synthetic features, and the gradient (forward,
+    backward, one weight-gradient partial per 64-row workgroup and their
+    fixed-order reduction) on the training batch (4096 rows) and on 65,536
+    rows; three timed calls each after one untimed, HIP events on the
+    current stream.  Algorithmic work per row: 68,096 FLOP forward
+    (6-128-128-128-4 matrix products), three times that for the gradient."""
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(5)
+    net = Q.MLP(seed=11, device=0)
+    flop_fwd = 2 * (6 * 128 + 128 * 128 + 128 * 128 + 128 * 4)
+    out = {"probe": "mlp", "flop_per_row_forward": flop_fwd}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 3
+
+    for name, n, mult in (("forward", args.probe_mlp_rows, 1), ("gradient_4096", 4096, 3),
+                          ("gradient_65536", 65536, 3)):
+        x = torch.rand((n, Q.MLP_NIN), dtype=torch.float32, device="cuda:0", generator=g)
+        y = torch.randint(0, Q.MLP_NOUT, (n,), dtype=torch.int32, device="cuda:0", generator=g)
+        fn = (lambda: net.forward(x)) if mult == 1 else (lambda: net.gradient(x, y))
+        ms = timed(fn)
+        tf = mult * flop_fwd * n / (ms * 1e-3) / 1e12
+        out[name] = {"rows": n, "ms": ms, "tflops": tf, "frac_bf16_dense_peak": tf / 2500.0}
+    return out
+
+
 def outcomes_by_status(np, lab, status):
     """Counts of each outcome label by the stop status that ended the
     trajectory (nonzero entries only)."""
@@ -244,7 +283,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     if args.probe != "none":
-        res = probe_flops(args, W, Q, torch) if args.probe == "flops" else probe_copy(args, torch)
+        res = (probe_flops(args, W, Q, torch) if args.probe == "flops" else
+               probe_mlp(args, Q, torch) if args.probe == "mlp" else probe_copy(args, torch))
         print(json.dumps(res), flush=True)
         return
     wl = W.CONFIGS[args.workload]()
