@@ -404,6 +404,7 @@ def main():
                      "traffic": TRAFFIC.get((wl.name, kernel)),
                      "kernel": kernel, "timed_ms": prop_ms, "trial_steps": trial_steps,
                      "flop_per_trial_step": fs["hand"],
+                     "flop_per_trial_step_hand": fs["hand"], "frac_hand": achieved / peak,
                      "flop_per_trial_step_method": fs["method"],
                      "frac_method": rate * fs["method"] / PEAK_FP64_VECTOR,
                      "flop_per_trial_step_counter": fs["counter"],
