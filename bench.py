@@ -80,7 +80,7 @@ def parse():
                          "(0: the workload's default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-procs", type=int, default=16,
-                    help="processes of the CPU baseline pool (the GPU box's host share)")
+                    help="processes of the CPU baseline pool (the host's share of cores)")
     ap.add_argument("--rk", default="dop853", choices=list(RK_NAMES),
                     help="Runge-Kutta variant of the adaptive integrator")
     ap.add_argument("--atol", type=float, default=None, help="override the workload's atol")
