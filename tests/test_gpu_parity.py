@@ -150,7 +150,7 @@ def _first_step_difference(log, tmax, gpu_times, rel=1e-3):
     return None if len(ho) == len(hg) else m + 1
 
 
-def _short_horizon(Q, torch, orc, wl, ids, periods, **prm):
+def _short_horizon(Q, torch, orc, wl, ids, periods, horizon_cap=math.inf, **prm):
     """GPU and oracle integrate the same initial states over a few periods:
     every final state agrees to 1e-9 relative, whatever the two step
     sequences do.  The sequences are compared through the GPU's accepted
@@ -170,7 +170,7 @@ def _short_horizon(Q, torch, orc, wl, ids, periods, **prm):
     oprm = orc.make_params(p)
     which = _inst_of(wl, ids)
     levs = {k: orc.level(sys, wl.instances[k].v, wl.instances[k].j) for k in set(which)}
-    T = np.array([periods * levs[k][3] for k in which])
+    T = np.array([min(periods * levs[k][3], horizon_cap) for k in which])
     st.d[Q.F_TMAX] = torch.as_tensor(T, device="cuda:0")
     st.d[Q.F_RSTOP].fill_(1e9)
     rec_max = 4096
@@ -248,6 +248,78 @@ def test_short_horizon_generic_kernel(Q, torch, orc, rk):
 def test_fixed_step_mode_matches(Q, torch, orc, rk):
     wl = W.config_batched(per_inst=4)
     _short_horizon(Q, torch, orc, wl, np.arange(0, 384, 5), 2.0, fixed_step=1, h_fixed=0.5, rk=rk)
+
+
+def _degenerate_workload():
+    """The method's edge cases on the H2 + Ca surface, 64 trajectories each:
+    a head-on collision (b = 0 fixed: the atom on the axis), the top bound
+    vibrational level (v = 16, near the dissociation limit, large amplitude),
+    the highest quasi-bound rotational level of v = 0 (j = 36, above the
+    dissociation limit behind the centrifugal barrier), a 1 K and a 1e5 K
+    collision, and a fixed impact parameter close to b_max."""
+    seed = 4242
+    spec = [(1.0e4, 0, 0, W.B_FIXED, 0.0), (1.0e4, 16, 0, W.B_AREA, 0.0),
+            (1.0e4, 0, 36, W.B_AREA, 0.0), (1.0, 0, 0, W.B_AREA, 0.0),
+            (1.0e5, 2, 5, W.B_AREA, 0.0), (1.0e4, 1, 3, W.B_FIXED, 9.99)]
+    inst, first = [], 0
+    for Ec, v, j, mode, b in spec:
+        inst.append(W.Instance(Ec, v, j, 64, first, seed, mode, b, 10.0))
+        first += 64
+    return W.Workload("degenerate", W.h2ca_system(), W.Params(), inst)
+
+
+def test_degenerate_instances_init(Q, torch, orc):
+    """Initial states of the edge-case instances equal the oracle's: draws
+    bit-exact, every field to 1e-13 relative plus the two sides' measured
+    difference of the level they start from (rho1 and P1 scale with r+,
+    rho2 and t_max with tau through Eq. (6)), which near the dissociation
+    limit (v = 16, j = 36) exceeds 1e-13; the level differences are held to
+    the level bars (E 1e-13, r+- 1e-12, tau 2e-12)."""
+    wl = _degenerate_workload()
+    ctx = _ctx(Q, wl)
+    ids = np.arange(wl.n_traj)
+    tid, st, smp = _gpu_init(Q, torch, ctx, ids)
+    torch.cuda.synchronize()
+    d, s = st.d.cpu().numpy(), smp.cpu().numpy()
+    assert np.all(st.status.cpu().numpy() == Q.RUNNING)
+    sys, prm = orc.make_system(wl.system), orc.make_params(wl.params)
+    which = _inst_of(wl, ids)
+    ks = sorted(set(which))
+    levs = {k: orc.level(sys, wl.instances[k].v, wl.instances[k].j) for k in ks}
+    assert levs[2][0] > 0.0          # the j = 36 level lies above the dissociation limit
+    g = ctx.levels([wl.instances[k].v for k in ks], [wl.instances[k].j for k in ks])
+    dlev = {}
+    for r, k in enumerate(ks):
+        rel = np.abs(g[r] / levs[k] - 1.0)
+        assert rel[0] < 1e-13 and rel[1] < 1e-12 and rel[2] < 1e-12 and rel[3] < 2e-12, (k, rel)
+        dlev[k] = max(rel[2], rel[3])
+    print("largest of r+ and tau, GPU against the oracle, per instance:",
+          {k: "%.1e" % v for k, v in dlev.items()})
+    worst = 0.0
+    for c, (i, k) in enumerate(zip(ids, which)):
+        I = wl.instances[k]
+        y, aux, sm = orc.init(sys, prm, orc.make_instance(I), levs[k], int(i))
+        assert np.array_equal(s[:5, c], sm[:5]), i
+        if I.b_mode == W.B_FIXED:
+            assert s[0, c] == I.b
+        rel = np.abs(d[:12, c] - y) / np.maximum(np.abs(y), 1.0)
+        worst = max(worst, rel.max())
+        assert rel.max() < 1e-13 + 2.0 * dlev[k], (i, rel, dlev[k])
+        assert d[Q.F_TMAX, c] == pytest.approx(aux[1], rel=1e-13 + 2.0 * dlev[k]), i
+    print("largest relative difference of the initial states %.1e" % worst)
+    # head-on: the atom starts on the axis, moving along it
+    head = which == 0
+    assert np.all(d[3, head] == 0.0) and np.all(d[4, head] == 0.0)
+    assert np.all(d[9, head] == 0.0) and np.all(d[10, head] == 0.0)
+
+
+@RK_VARIANTS
+def test_degenerate_instances_short_horizon(Q, torch, orc, rk):
+    """The edge-case instances integrated for three vibrational periods,
+    capped at 1000 atomic time units (before the atom reaches the molecule),
+    every final state within 1e-9 of the oracle's."""
+    wl = _degenerate_workload()
+    _short_horizon(Q, torch, orc, wl, np.arange(wl.n_traj), 3.0, horizon_cap=1000.0, rk=rk)
 
 
 # ----------------------------------------------------------------------------
