@@ -402,8 +402,6 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": TRAFFIC.get((wl.name, kernel)),
-                     "hbm_gbps": (TRAFFIC[(wl.name, kernel)] / (prop_ms * 1e-3) / 1e9
-                                  if (wl.name, kernel) in TRAFFIC else None),
                      "kernel": kernel, "timed_ms": prop_ms, "trial_steps": trial_steps,
                      "flop_per_trial_step": fs["hand"],
                      "flop_per_trial_step_hand": fs["hand"], "frac_hand": achieved / peak,
