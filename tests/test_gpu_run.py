@@ -322,12 +322,12 @@ def test_full_size_bench_configuration(Q, torch, orc):
     tolerances, quads chosen by run size, LPT, graph): every
     trajectory finishes inside the energy gate; sampled trajectories checked
     one by one against the oracle (draws bit-exact, classification of the
-    GPU's own final state bit-exact); per-channel probabilities of the full
-    run against the oracle's on a stratified subsample (every 25th id of
-    every instance): within 3 combined standard errors pooled over instances,
-    and per instance the oracle's count is consistent with the GPU's
-    probability (two-sided exact binomial test, p > 1e-4 for each of the
-    384 instance-channel pairs)."""
+    GPU's own final state bit-exact); channel probabilities of the full run
+    against the oracle's on a stratified subsample (42 ids of every
+    instance, 4032 trajectories), per collision energy and channel and per
+    instance and channel, by the exact binomial test at 3 standard errors
+    (at most the chance number of the comparisons beyond 3, none beyond
+    4.5), and pooled over all instances."""
     wl = W.config_batched()
     wl.params = W.gated_params(wl, W.RK_DOP853)
     ctx = Q.Context(wl.system, wl.params)
@@ -357,24 +357,15 @@ def test_full_size_bench_configuration(Q, torch, orc):
         if fin[c]:
             cl = orc.classify(sys, prm, r["d"][:12, c])
             assert (cl["label"], cl["vt"], cl["jt"]) == (lab[c], r["vt"][c], r["jt"][c]), c
-    per = [np.arange(I.first_id, I.first_id + I.n_traj, 25, dtype=np.int64) for I in wl.instances]
-    recs, w2 = orc.run_workload(wl, per, processes=8)
-    ref = orc.cross_sections(wl, recs["label"], np.ones(len(recs)), w2)
-    m = np.array([len(p) for p in per])
-    for ch in range(4):
-        # pooled over instances (equal weights: every instance has 1042 ids)
-        p_g = xs[:, 7 + ch].mean()
-        p_o = (ref["P"][:, ch] * m).sum() / m.sum()
-        se = math.sqrt(max(p_g * (1 - p_g), 1e-12) / n + max(p_o * (1 - p_o), 1e-12) / m.sum())
-        assert abs(p_g - p_o) <= 3 * se, (ch, p_g, p_o, se)
-        for k in range(len(wl.instances)):
-            ng = xs[k, 0]
-            pg = min(max(xs[k, 7 + ch], 0.5 / ng), 1.0 - 0.5 / ng)
-            ko = int(round(ref["P"][k, ch] * m[k]))
-            pv = stats.binomtest(ko, int(m[k]), pg).pvalue
-            assert pv > 1e-4, (ch, k, xs[k, 7 + ch], ko, int(m[k]), pv)
-    print("pooled P gpu", xs[:, 7:11].mean(axis=0), "oracle subsample",
-          (ref["P"] * m[:, None]).sum(axis=0) / m.sum())
+    ref = _per_energy_channels_vs_oracle(orc, wl, xs[:, :5], per_inst=42)
+    # per instance and channel: the oracle's count of 42 against the GPU's
+    # probability from 1042 trajectories
+    zs = []
+    for k in range(len(wl.instances)):
+        for ch in range(4):
+            zs.append((_binom_z(int(round(float(ref["P"][k, ch] * 42))), 42, xs[k, 1 + ch], xs[k, 0]),
+                       k, ch))
+    _assert_z(zs, "(instance, channel)")
 
 
 def _full_size_run(Q, torch, orc, wl, n_expect, seed):
@@ -425,6 +416,34 @@ def _full_size_run(Q, torch, orc, wl, n_expect, seed):
     return lab, ids, xs
 
 
+def _binom_z(x_o, m, x_g, n_g):
+    """Normal deviate of the two-sided exact binomial p-value of the
+    oracle's x_o successes in m draws at the GPU's probability x_g / n_g
+    (z <= 3: within 3 standard errors, also for the small counts of rare
+    channels).  The GPU's estimate is taken as the probability (it comes
+    from many times more trajectories), kept half a count away from 0 and 1
+    so that a channel the GPU run never (or always) saw is tested at the
+    largest (smallest) probability such a count leaves open instead of at
+    exactly 0 (1)."""
+    p_g = min(max(x_g, 0.5), n_g - 0.5) / n_g
+    pv = stats.binomtest(x_o, m, p_g).pvalue
+    return float(stats.norm.isf(pv / 2.0)) if pv < 1.0 else 0.0
+
+
+def _assert_z(zs, what):
+    """With K comparisons about 0.27 % lie beyond 3 by chance: the number
+    beyond 3 may not exceed the 99.9 % quantile of Binomial(K, 0.0027), and
+    none may exceed 4.5."""
+    z = np.array([q[0] for q in zs])
+    K = len(z)
+    allowed = int(stats.binom.ppf(0.999, K, 0.0027))
+    beyond = [q for q in zs if q[0] > 3.0]
+    print("%d %s comparisons: largest z %.2f, %d beyond 3 (allowed %d); the largest five: %s"
+          % (K, what, z.max(), len(beyond), allowed, sorted(zs, key=lambda q: -q[0])[:5]))
+    assert len(beyond) <= allowed, beyond
+    assert z.max() <= 4.5, max(zs, key=lambda q: q[0])
+
+
 def _per_energy_channels_vs_oracle(orc, wl, xs, per_inst):
     """Eq. (16), (18): per collision energy and channel, the GPU's full run
     against the oracle's on a stratified subsample (the same number of ids
@@ -450,22 +469,11 @@ def _per_energy_channels_vs_oracle(orc, wl, xs, per_inst):
         n_g = ng[rows].sum()
         m = per_inst * len(rows)
         for ch in range(4):
-            p_g = xs[rows, 1 + ch].sum() / n_g
+            x_g = xs[rows, 1 + ch].sum()
             x_o = int(round(float((ref["P"][rows, ch] * per_inst).sum())))
-            pv = stats.binomtest(x_o, m, p_g).pvalue if 0.0 < p_g < 1.0 else float(
-                x_o == (m if p_g == 1.0 else 0))
-            z = float(stats.norm.isf(pv / 2.0)) if pv < 1.0 else 0.0
-            zs.append((z, E, ch, p_g, x_o / m))
-    z = np.array([q[0] for q in zs])
-    K = len(z)
-    allowed = int(stats.binom.ppf(0.999, K, 0.0027))
-    beyond = [q for q in zs if q[0] > 3.0]
-    print("%d (E_c, channel) comparisons: largest z %.2f, %d beyond 3 (allowed %d); the "
-          "largest five (z, E_c, channel, P gpu, P oracle): %s"
-          % (K, z.max(), len(beyond), allowed,
-             ["%.2f %.4g %d %.4f %.4f" % q for q in sorted(zs, reverse=True)[:5]]))
-    assert len(beyond) <= allowed, beyond
-    assert z.max() <= 4.5, max(zs)
+            zs.append((_binom_z(x_o, m, x_g, n_g), "%.4g" % E, ch, "%.4f" % (x_g / n_g),
+                       "%.4f" % (x_o / m)))
+    _assert_z(zs, "(E_c, channel)")
     n = ng.sum()
     m = per_inst * len(wl.instances)
     for ch in range(4):
@@ -476,6 +484,7 @@ def _per_energy_channels_vs_oracle(orc, wl, xs, per_inst):
         assert abs(x_g / n - x_o / m) <= 3 * se, (ch, x_g / n, x_o / m, se)
     print("pooled P gpu", xs[:, 1:5].sum(axis=0) / n, "oracle subsample",
           (ref["P"] * per_inst).sum(axis=0) / m, "oracle trajectories", m)
+    return ref
 
 
 def test_full_size_mixed_configuration(Q, torch, orc):
