@@ -138,22 +138,124 @@ __device__ inline void load_x16(const float* x, const int32_t* idx, int64_t row0
 
 // ---------------------------------------------------------------------------
 // inference: probabilities of the four classes
+//
+// Each workgroup copies the forward weights (bf16) and biases into LDS once
+// and then walks groups of 64 rows (one 16-row tile per wave) with a
+// grid-stride loop, so every MFMA takes its weight fragment from LDS rather
+// than from the cache.  LDS rows are padded by 8 bf16 (16 bytes): the 16 rows
+// of a fragment then start in different banks.  The arithmetic is that of
+// the training kernel's forward pass (the same MFMA sequence over k, bias,
+// ReLU and bf16 rounding per layer).
 // ---------------------------------------------------------------------------
+constexpr int kLdIn = kInP + 8;    // padded LDS row strides (elements)
+constexpr int kLdHid = kHid + 8;
+
+// The lanes of one wave exchange rows through LDS: its LDS operations run
+// in order, so it is enough that the compiler keeps them in order and that
+// the stores have completed.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Dense layer on one wave's 16 rows with LDS operands: out = act(in W + b).
+template <int K, bool Relu>
+__device__ inline void dense16_lds(const __bf16* in, int ldi, const __bf16* wf, int ldw,
+                                   const float* bias, __bf16* out, int ldo, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < kHid / 16; ++t) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < K; kk += 32)
+            acc = mfma(frag_rows(in, ldi, 0, kk, lane), frag_rows(wf, ldw, 16 * t, kk, lane), acc);
+        const int j = 16 * t + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = 4 * (lane >> 4) + e;
+            float z = acc[e] + bias[j];
+            if (Relu) z = fmaxf(z, 0.f);
+            out[i * ldo + j] = to_bf16(z);
+        }
+    }
+}
+
+// rows x cols bf16 matrix (16-byte rows chunks) from global into LDS with a
+// padded row stride
+__device__ inline void stage_rows(const __bf16* src, int rows, int cols, __bf16* dst, int ld, int tid)
+{
+    const int chunks = cols / 8;
+    for (int q = tid; q < rows * chunks; q += 256) {
+        const int r = q / chunks, c = q % chunks;
+        *reinterpret_cast<bf16x8*>(dst + r * ld + 8 * c) =
+            *reinterpret_cast<const bf16x8*>(src + r * cols + 8 * c);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_mlp_forward(Weights W, const float* x, int64_t n, float* prob)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 s_x[4][16 * kInP];
-    __shared__ __attribute__((aligned(16))) __bf16 s_h[3][4][16 * kHid];
+    __shared__ __attribute__((aligned(16))) __bf16 s_w1[kHid * kLdIn];
+    __shared__ __attribute__((aligned(16))) __bf16 s_w2[kHid * kLdHid];
+    __shared__ __attribute__((aligned(16))) __bf16 s_w3[kHid * kLdHid];
+    __shared__ __attribute__((aligned(16))) __bf16 s_w4[kOutP * kLdHid];
+    __shared__ float s_b[3 * kHid + kOut];
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[4][16 * kLdIn];
+    __shared__ __attribute__((aligned(16))) __bf16 s_h[2][4][16 * kLdHid];
     __shared__ float s_lg[4][16 * kOut];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t row0 = (int64_t)blockIdx.x * kTile + 16 * wave;
-    load_x16(x, nullptr, row0, n, s_x[wave], lane);
-    forward16(W, s_x[wave], s_h[0][wave], s_h[1][wave], s_h[2][wave], s_lg[wave], lane);
-    if (lane < 16 && row0 + lane < n) {
-        const float* z = s_lg[wave] + lane * kOut;
-        const float m = fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3]));
-        float e[kOut], s = 0.f;
-        for (int c = 0; c < kOut; ++c) { e[c] = expf(z[c] - m); s += e[c]; }
-        for (int c = 0; c < kOut; ++c) prob[(row0 + lane) * kOut + c] = e[c] / s;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    stage_rows(W.w1f, kHid, kInP, s_w1, kLdIn, tid);
+    stage_rows(W.w2f, kHid, kHid, s_w2, kLdHid, tid);
+    stage_rows(W.w3f, kHid, kHid, s_w3, kLdHid, tid);
+    stage_rows(W.w4f, kOutP, kHid, s_w4, kLdHid, tid);
+    for (int q = tid; q < kHid; q += 256) {
+        s_b[q] = W.theta[ob1 + q];
+        s_b[kHid + q] = W.theta[ob2 + q];
+        s_b[2 * kHid + q] = W.theta[ob3 + q];
+    }
+    if (tid < kOut) s_b[3 * kHid + tid] = W.theta[ob4 + tid];
+    __syncthreads();
+    const int64_t groups = (n + kTile - 1) / kTile;
+    // each wave works on its own LDS rows: the waves need not wait for each other
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int64_t row0 = g * kTile + 16 * wave;
+        __bf16* xw = s_x[wave];
+        for (int q = lane; q < 16 * kInP; q += 64) {
+            const int i = q / kInP, k = q % kInP;
+            const int64_t r = row0 + i;
+            float v = 0.f;
+            if (r < n && k < kIn) v = x[r * kIn + k];
+            xw[i * kLdIn + k] = to_bf16(v);
+        }
+        wave_lds_sync();
+        dense16_lds<kInP, true>(xw, kLdIn, s_w1, kLdIn, s_b, s_h[0][wave], kLdHid, lane);
+        wave_lds_sync();
+        dense16_lds<kHid, true>(s_h[0][wave], kLdHid, s_w2, kLdHid, s_b + kHid, s_h[1][wave], kLdHid, lane);
+        wave_lds_sync();
+        dense16_lds<kHid, true>(s_h[1][wave], kLdHid, s_w3, kLdHid, s_b + 2 * kHid, s_h[0][wave], kLdHid,
+                                lane);
+        wave_lds_sync();
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < kHid; kk += 32)
+            acc = mfma(frag_rows(s_h[0][wave], kLdHid, 0, kk, lane), frag_rows(s_w4, kLdHid, 0, kk, lane), acc);
+        const int j = lane & 15;
+        if (j < kOut) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                s_lg[wave][(4 * (lane >> 4) + e) * kOut + j] = acc[e] + s_b[3 * kHid + j];
+        }
+        wave_lds_sync();
+        if (lane < 16 && row0 + lane < n) {
+            const float* z = s_lg[wave] + lane * kOut;
+            const float m = fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3]));
+            float e[kOut], sum = 0.f;
+            for (int c = 0; c < kOut; ++c) { e[c] = expf(z[c] - m); sum += e[c]; }
+            for (int c = 0; c < kOut; ++c) prob[(row0 + lane) * kOut + c] = e[c] / sum;
+        }
+        wave_lds_sync();
     }
 }
 
@@ -399,6 +501,7 @@ __global__ void k_mlp_init(float* theta, uint64_t seed)
 // ---------------------------------------------------------------------------
 struct qcams_mlp {
     int device = 0;
+    int n_cu = 256;   // compute units of the device (forward grid)
     float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
     float* partial = nullptr;
     float* loss_part = nullptr;
@@ -483,6 +586,9 @@ int qcams_mlp_create(qcams_mlp** out, int device, const float* params, uint64_t 
         delete m;
         return mfail(nullptr, QCAMS_EHIP, "hipSetDevice failed");
     }
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+        m->n_cu = cu;
     bool ok = hipMalloc(&m->theta, kNParam * sizeof(float)) == hipSuccess &&
               hipMalloc(&m->m, kNParam * sizeof(float)) == hipSuccess &&
               hipMalloc(&m->v, kNParam * sizeof(float)) == hipSuccess &&
@@ -564,8 +670,12 @@ int qcams_mlp_forward(qcams_mlp* m, const float* x, int64_t n, float* prob, void
     if (!m || n < 0 || (n > 0 && (!x || !prob))) return mfail(m, QCAMS_EINVAL, "bad arguments");
     if (n == 0) return QCAMS_OK;
     MHIP(m, hipSetDevice(m->device));
-    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((n + kTile - 1) / kTile)), dim3(256), 0,
-                       (hipStream_t)stream, weights_of(m), x, n, prob);
+    // one resident workgroup per CU (the LDS copy of the weights): as many
+    // workgroups as CUs, or fewer for small n
+    const int64_t groups = (n + kTile - 1) / kTile;
+    const int64_t grid = groups < m->n_cu ? groups : m->n_cu;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
+                       weights_of(m), x, n, prob);
     MHIP(m, hipGetLastError());
     return QCAMS_OK;
 }
