@@ -140,7 +140,7 @@ __device__ inline void load_x16(const float* x, const int32_t* idx, int64_t row0
 // inference: probabilities of the four classes
 //
 // Each workgroup copies the forward weights (bf16) and biases into LDS once
-// and then walks groups of 64 rows (one 16-row tile per wave) with a
+// and then walks groups of 128 rows (two 16-row tiles per wave) with a
 // grid-stride loop, so every MFMA takes its weight fragment from LDS rather
 // than from the cache.  LDS rows are padded by 8 bf16 (16 bytes): the 16 rows
 // of a fragment then start in different banks.  The arithmetic is that of
@@ -161,29 +161,55 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Dense layer on one wave's 16 rows with LDS operands: out = act(in W + b).
+// Dense layer on one wave's 32 rows (two 16-row tiles) with LDS operands:
+// out = act(in W + b), computed transposed (out^T = W^T in^T: the weight
+// fragment is the MFMA's A operand, the rows' fragment its B operand), so
+// that each lane receives four consecutive output features of one row and
+// stores them with one 8-byte write.  All input fragments are read before
+// the first output is written, so `out` may be `in` (in place); the two
+// tiles' MFMA chains run side by side.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 template <int K, bool Relu>
-__device__ inline void dense16_lds(const __bf16* in, int ldi, const __bf16* wf, int ldw,
+__device__ inline void dense32_lds(const __bf16* in, int ldi, const __bf16* wf, int ldw,
                                    const float* bias, __bf16* out, int ldo, int lane)
 {
+    constexpr int KB = K / 32;
+    bf16x8 h[2][KB];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) h[r][kb] = frag_rows(in, ldi, 16 * r, 32 * kb, lane);
+    floatx4 acc[2][kHid / 16];
 #pragma unroll
     for (int t = 0; t < kHid / 16; ++t) {
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc[0][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc[1][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < K; kk += 32)
-            acc = mfma(frag_rows(in, ldi, 0, kk, lane), frag_rows(wf, ldw, 16 * t, kk, lane), acc);
-        const int j = 16 * t + (lane & 15);
+        for (int kb = 0; kb < KB; ++kb) {
+            const bf16x8 w = frag_rows(wf, ldw, 16 * t, 32 * kb, lane);
+            acc[0][t] = mfma(w, h[0][kb], acc[0][t]);
+            acc[1][t] = mfma(w, h[1][kb], acc[1][t]);
+        }
+    }
+    const int i0 = lane & 15, j0 = 4 * (lane >> 4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int i = 4 * (lane >> 4) + e;
-            float z = acc[e] + bias[j];
-            if (Relu) z = fmaxf(z, 0.f);
-            out[i * ldo + j] = to_bf16(z);
+    for (int t = 0; t < kHid / 16; ++t) {
+        const floatx4 bj = *reinterpret_cast<const floatx4*>(bias + 16 * t + j0);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            bf16x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float z = acc[r][t][e] + bj[e];
+                if (Relu) z = fmaxf(z, 0.f);
+                o[e] = to_bf16(z);
+            }
+            *reinterpret_cast<bf16x4*>(out + (16 * r + i0) * ldo + 16 * t + j0) = o;
         }
     }
 }
 
-// rows x cols bf16 matrix (16-byte rows chunks) from global into LDS with a
+// rows x cols bf16 matrix (16-byte row chunks) from global into LDS with a
 // padded row stride
 __device__ inline void stage_rows(const __bf16* src, int rows, int cols, __bf16* dst, int ld, int tid)
 {
@@ -195,16 +221,18 @@ __device__ inline void stage_rows(const __bf16* src, int rows, int cols, __bf16*
     }
 }
 
+constexpr int kFwdRows = 32;               // rows per wave per iteration
+constexpr int kFwdTile = 4 * kFwdRows;     // rows per workgroup per iteration
+
 __global__ void __launch_bounds__(256) k_mlp_forward(Weights W, const float* x, int64_t n, float* prob)
 {
     __shared__ __attribute__((aligned(16))) __bf16 s_w1[kHid * kLdIn];
     __shared__ __attribute__((aligned(16))) __bf16 s_w2[kHid * kLdHid];
     __shared__ __attribute__((aligned(16))) __bf16 s_w3[kHid * kLdHid];
     __shared__ __attribute__((aligned(16))) __bf16 s_w4[kOutP * kLdHid];
-    __shared__ float s_b[3 * kHid + kOut];
-    __shared__ __attribute__((aligned(16))) __bf16 s_x[4][16 * kLdIn];
-    __shared__ __attribute__((aligned(16))) __bf16 s_h[2][4][16 * kLdHid];
-    __shared__ float s_lg[4][16 * kOut];
+    __shared__ __attribute__((aligned(16))) float s_b[3 * kHid + kOut];
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[4][kFwdRows * kLdIn];
+    __shared__ __attribute__((aligned(16))) __bf16 s_h[4][kFwdRows * kLdHid];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     stage_rows(W.w1f, kHid, kInP, s_w1, kLdIn, tid);
     stage_rows(W.w2f, kHid, kHid, s_w2, kLdHid, tid);
@@ -217,12 +245,13 @@ __global__ void __launch_bounds__(256) k_mlp_forward(Weights W, const float* x, 
     }
     if (tid < kOut) s_b[3 * kHid + tid] = W.theta[ob4 + tid];
     __syncthreads();
-    const int64_t groups = (n + kTile - 1) / kTile;
+    const int64_t groups = (n + kFwdTile - 1) / kFwdTile;
+    __bf16* xw = s_x[wave];
+    __bf16* hw = s_h[wave];
     // each wave works on its own LDS rows: the waves need not wait for each other
     for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
-        const int64_t row0 = g * kTile + 16 * wave;
-        __bf16* xw = s_x[wave];
-        for (int q = lane; q < 16 * kInP; q += 64) {
+        const int64_t row0 = g * kFwdTile + kFwdRows * wave;
+        for (int q = lane; q < kFwdRows * kInP; q += 64) {
             const int i = q / kInP, k = q % kInP;
             const int64_t r = row0 + i;
             float v = 0.f;
@@ -230,30 +259,35 @@ __global__ void __launch_bounds__(256) k_mlp_forward(Weights W, const float* x, 
             xw[i * kLdIn + k] = to_bf16(v);
         }
         wave_lds_sync();
-        dense16_lds<kInP, true>(xw, kLdIn, s_w1, kLdIn, s_b, s_h[0][wave], kLdHid, lane);
+        dense32_lds<kInP, true>(xw, kLdIn, s_w1, kLdIn, s_b, hw, kLdHid, lane);
         wave_lds_sync();
-        dense16_lds<kHid, true>(s_h[0][wave], kLdHid, s_w2, kLdHid, s_b + kHid, s_h[1][wave], kLdHid, lane);
+        dense32_lds<kHid, true>(hw, kLdHid, s_w2, kLdHid, s_b + kHid, hw, kLdHid, lane);
         wave_lds_sync();
-        dense16_lds<kHid, true>(s_h[1][wave], kLdHid, s_w3, kLdHid, s_b + 2 * kHid, s_h[0][wave], kLdHid,
-                                lane);
+        dense32_lds<kHid, true>(hw, kLdHid, s_w3, kLdHid, s_b + 2 * kHid, hw, kLdHid, lane);
         wave_lds_sync();
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        // logits, transposed: lane l < 16 receives the four class logits of
+        // row l of each tile; the softmax needs no exchange
+        floatx4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-        for (int kk = 0; kk < kHid; kk += 32)
-            acc = mfma(frag_rows(s_h[0][wave], kLdHid, 0, kk, lane), frag_rows(s_w4, kLdHid, 0, kk, lane), acc);
-        const int j = lane & 15;
-        if (j < kOut) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                s_lg[wave][(4 * (lane >> 4) + e) * kOut + j] = acc[e] + s_b[3 * kHid + j];
+        for (int kk = 0; kk < kHid; kk += 32) {
+            const bf16x8 w = frag_rows(s_w4, kLdHid, 0, kk, lane);
+            acc[0] = mfma(w, frag_rows(hw, kLdHid, 0, kk, lane), acc[0]);
+            acc[1] = mfma(w, frag_rows(hw, kLdHid, 16, kk, lane), acc[1]);
         }
-        wave_lds_sync();
-        if (lane < 16 && row0 + lane < n) {
-            const float* z = s_lg[wave] + lane * kOut;
-            const float m = fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3]));
-            float e[kOut], sum = 0.f;
-            for (int c = 0; c < kOut; ++c) { e[c] = expf(z[c] - m); sum += e[c]; }
-            for (int c = 0; c < kOut; ++c) prob[(row0 + lane) * kOut + c] = e[c] / sum;
+        if (lane < 16) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int64_t row = row0 + 16 * r + lane;
+                if (row < n) {
+                    float z[kOut];
+#pragma unroll
+                    for (int c = 0; c < kOut; ++c) z[c] = acc[r][c] + s_b[3 * kHid + c];
+                    const float m = fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3]));
+                    float e[kOut], sum = 0.f;
+                    for (int c = 0; c < kOut; ++c) { e[c] = expf(z[c] - m); sum += e[c]; }
+                    for (int c = 0; c < kOut; ++c) prob[row * kOut + c] = e[c] / sum;
+                }
+            }
         }
         wave_lds_sync();
     }
@@ -672,7 +706,7 @@ int qcams_mlp_forward(qcams_mlp* m, const float* x, int64_t n, float* prob, void
     MHIP(m, hipSetDevice(m->device));
     // one resident workgroup per CU (the LDS copy of the weights): as many
     // workgroups as CUs, or fewer for small n
-    const int64_t groups = (n + kTile - 1) / kTile;
+    const int64_t groups = (n + kFwdTile - 1) / kFwdTile;
     const int64_t grid = groups < m->n_cu ? groups : m->n_cu;
     hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
                        weights_of(m), x, n, prob);
